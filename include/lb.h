@@ -1,0 +1,174 @@
+/*
+ * lb.h -- C ABI of the MI355X (gfx950) two-belt Shan-Chen lattice Boltzmann
+ * library (liblb.so).
+ *
+ * The method is the one of Chibbaro, Falcucci, Chen, Shan, Chiatti, Succi,
+ * "Lattice Boltzmann models for non-ideal fluids with arrested
+ * phase-separation": a D2Q9 BGK lattice Boltzmann equation (eq. 1, section II)
+ * on a periodic nx-by-ny lattice, driven by the two-belt pseudopotential force
+ * of eq. (FORCE) (section III, Table 1) with psi(rho) = sqrt(rho0)
+ * (1 - exp(-rho/rho0)), and monitored through the pseudo-potential energies
+ * E_s, E_m and E_bulk of section V.
+ *
+ * One time step t -> t+1 at every site x:
+ *   rho = sum_i f_i,  j = sum_i c_i f_i                        (section II)
+ *   F   = -psi(x) sum_{k=1}^{24} K_k psi(x + c_k) c_k          (eq. FORCE)
+ *         K_k = G1 w_k + G2 p(|c_k|^2) on the 8 first-belt links,
+ *         K_k = G2 p(|c_k|^2) on the 16 second-belt links      (Table 1)
+ *   u_eq = (j + tau F) / rho              (Shan-Chen velocity shift)
+ *   f_i(x + c_i, t+1) = f_i - (f_i - f_i^eq(rho, u_eq)) / tau  (eq. 1)
+ *
+ * Conventions shared by every call:
+ *   - Every function returns LB_OK (0) on success and a negative lb_status
+ *     on failure; lb_last_error() then holds a message (per thread).
+ *     Arguments are checked on the host before anything is launched, and a
+ *     call that fails leaves the context unchanged.  Nothing is thrown
+ *     across this boundary.
+ *   - Scalar fields are dense row-major double arrays of ny*nx values,
+ *     site (x, y) at index y*nx + x.  Population arrays are dense
+ *     [9][ny][nx] arrays of the storage type, population i in the D2Q9 order
+ *     (0,0) (1,0) (0,1) (-1,0) (0,-1) (1,1) (-1,1) (-1,-1) (1,-1).
+ *   - Ownership: the caller owns every buffer it passes, including the
+ *     device workspace, which the context borrows until lb_destroy.  The
+ *     library owns only the small host-side context and allocates no device
+ *     memory of its own.
+ *   - Streams: a context issues all its work on the HIP stream given to
+ *     lb_init (NULL = the null stream).  lb_step is asynchronous; calls that
+ *     hand results to host memory synchronise the stream before returning.
+ *     A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LB_H
+#define LB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lb_ctx lb_ctx;
+
+/* Population storage.  LB_F64: double storage and arithmetic.  LB_F32:
+ * float storage and arithmetic.  LB_F16DEV: half-precision storage of the
+ * deviation f_i - w_i rho_ref, float arithmetic.  Global sums (mass and
+ * energies) are accumulated in double for every storage. */
+enum lb_storage { LB_F64 = 0, LB_F32 = 1, LB_F16DEV = 2 };
+
+enum lb_status {
+    LB_OK = 0,
+    LB_ERR_INVALID = -1,   /* bad argument, sizes or parameters            */
+    LB_ERR_HIP = -2,       /* HIP runtime error, or no usable device       */
+    LB_ERR_NONFINITE = -3, /* a returned mass or energy is not finite      */
+    LB_ERR_STATE = -4      /* unknown/destroyed context, full trace buffer */
+};
+
+typedef struct lb_params {
+    int32_t nx, ny;      /* periodic lattice; each >= 5 so the +-2 links of the
+                            second belt never alias onto one site; nx*ny < 2^31 */
+    int32_t storage;     /* lb_storage                                           */
+    int32_t log_every;   /* > 0: record the section V energies every log_every
+                            steps into the trace; 0: no trace                    */
+    int32_t tile_x;      /* columns per workgroup: 0 (library choice), 64, 128
+                            or 256                                               */
+    int32_t tile_y;      /* rows per workgroup: 0 (library choice) or 1..4096    */
+    int64_t trace_cap;   /* rows the trace can hold (>= 0)                       */
+    double tau;          /* BGK relaxation time, > 0.5 (the paper uses 1)        */
+    double rho0;         /* psi scale, > 0 (the paper fixes rho0 = 1)            */
+    double G1, G2;       /* first- and second-belt couplings, G < 0 attracts     */
+    double rho_ref;      /* LB_F16DEV only: populations are stored as
+                            f_i - w_i rho_ref (use the mean initial density)     */
+} lb_params;
+
+/* Bytes of device workspace a context with these parameters needs, or 0 if
+ * the parameters are invalid (host only; no device call). */
+size_t lb_workspace_bytes(const lb_params* p);
+
+/* LB_OK if the parameters are valid, LB_ERR_INVALID otherwise (host only). */
+int lb_validate(const lb_params* p);
+
+/* Resolved launch shape for these parameters: columns and rows per
+ * workgroup and the workgroup count of the step kernel (host only). */
+int lb_launch_shape(const lb_params* p, int32_t* tile_x, int32_t* tile_y,
+                    int32_t* blocks);
+
+/* Create a context at t = 0 whose populations are the equilibrium
+ * f_i^eq(rho_init, u_init) of section II (the paper starts from a fluid at
+ * rest, section IV).
+ *   workspace/bytes: device memory of at least lb_workspace_bytes(p) bytes,
+ *       256-byte aligned, owned by the caller and borrowed until lb_destroy.
+ *   rho_init: ny*nx densities, finite and > 0.
+ *   ux_init, uy_init: ny*nx velocities or NULL for 0.
+ *   inputs_on_device: 1 if the three input arrays are device pointers,
+ *       0 if they are host memory (copied before lb_init returns).
+ *   hip_stream: the hipStream_t all work of this context is issued on.
+ * Errors: LB_ERR_INVALID (parameters, NULL pointers, short workspace,
+ * non-finite or non-positive density), LB_ERR_HIP (no device, HIP error). */
+int lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t bytes,
+            const double* rho_init, const double* ux_init,
+            const double* uy_init, int inputs_on_device, void* hip_stream);
+
+/* Advance n >= 0 time steps of eq. (1) (t += n), asynchronously on the
+ * context's stream.  With log_every > 0, the energies of every state
+ * t' in [t, t+n) with t' % log_every == 0 that has not been recorded yet are
+ * appended to the trace, computed by the step that leaves t' (the state at
+ * t' is the pre-collision state, t' = 0 being the initial state); the state
+ * reached at t+n is recorded by the next step or by lb_trace.  LB_ERR_STATE,
+ * with nothing launched, if the trace cannot hold the new rows. */
+int lb_step(lb_ctx* c, int64_t n);
+
+/* Macroscopic fields of the state at the current t (section II):
+ * rho = sum_i f_i and u = j / rho with j = sum_i c_i f_i.  Outputs are ny*nx
+ * doubles each, device pointers if on_device = 1 (asynchronous), host
+ * otherwise (synchronous).  Any output may be NULL to skip it. */
+int lb_moments(lb_ctx* c, double* rho, double* ux, double* uy, int on_device);
+
+/* Section V observables of the state at the current t, synchronously:
+ * out = {t, M = sum rho, E_s, E_m, sum psi^2, E_bulk = (G1+G2)/2 sum psi^2},
+ * with E_s = 1/2 sum_x psi(x) sum_{i=0}^{8} (G1 w_i + G2 p_si) psi(x + c_i)
+ * (rest weight p_s0 = 247/420 from eq. weights_1) and
+ * E_m = 1/2 sum_x psi(x) sum_{i=1}^{16} G2 p_mi psi(x + c_mi).
+ * Sums are in double, in an order fixed by the launch shape, so repeated
+ * runs give bit-identical values.  LB_ERR_NONFINITE if any value is not
+ * finite (out is still written). */
+int lb_pseudo_energy(lb_ctx* c, double out[6]);
+
+/* Copy up to cap trace rows (6 doubles each, same layout as
+ * lb_pseudo_energy) into host memory; *n_rows receives the number of rows
+ * recorded so far.  If the current t is a log point not recorded yet and the
+ * trace has room, it is recorded first.  Synchronises the stream.
+ * LB_ERR_NONFINITE if a copied row holds a non-finite value. */
+int lb_trace(lb_ctx* c, double* out, int64_t cap, int64_t* n_rows);
+
+/* Current time step t. */
+int lb_time(lb_ctx* c, int64_t* t);
+
+/* Export the pre-collision populations at t as a dense [9][ny][nx] array of
+ * the storage type (for LB_F16DEV: the stored half deviations), to device
+ * memory if on_device = 1 (asynchronous) or host memory (synchronous). */
+int lb_get_state(lb_ctx* c, void* dst, int on_device);
+
+/* Replace the state with populations in the lb_get_state layout and set the
+ * time to t >= 0; the trace keeps its rows.  A lb_get_state / lb_set_state
+ * round trip is exact. */
+int lb_set_state(lb_ctx* c, const void* src, int on_device, int64_t t);
+
+/* The link tables the kernels use, for the given couplings (host only):
+ * cx, cy of the 24 links (first belt in D2Q9 order, then the second belt by
+ * |c|^2 = 4, 5, 8, counter-clockwise from +x), K[k] their couplings, KE[0]
+ * the rest coupling of E_s (G1 w_0 + G2 p_s0) and KE[1+k] = K[k]. */
+int lb_tables(const lb_params* p, int8_t cx[24], int8_t cy[24], double K[24],
+              double KE[25]);
+
+/* Release the context (after synchronising its stream).  The workspace is
+ * the caller's to free afterwards. */
+int lb_destroy(lb_ctx* c);
+
+/* Message describing the last failure on the calling thread. */
+const char* lb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LB_H */

@@ -30,6 +30,7 @@ def lib(precision="f64"):
         L.orc_d2q9.argtypes = [_vp, _vp, _vp]
         L.orc_tables.argtypes = [_vp, _vp, _vp, _vp, _dbl, _dbl]
         L.orc_real_bytes.restype = ctypes.c_int
+        L.orc_threads.restype = ctypes.c_int
         L.orc_init.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp]
         L.orc_moments.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp]
         L.orc_psi.argtypes = [_i64, _dbl, _vp, _vp]
@@ -55,6 +56,11 @@ def _p(a):
 
 def _field(a, dt):
     return np.ascontiguousarray(a, dtype=dt)
+
+
+def threads(precision="f64"):
+    """OpenMP threads the oracle's loops run on."""
+    return lib(precision).orc_threads()
 
 
 def d2q9():

@@ -32,6 +32,7 @@
  *     links only.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -159,6 +160,9 @@ void orc_tables(int8_t cx[24], int8_t cy[24], double K[24], double KE[25],
 }
 
 int orc_real_bytes(void) { return (int)sizeof(real); }
+
+/* Threads the OpenMP loops of this library use (for timing reports). */
+int orc_threads(void) { return omp_get_max_threads(); }
 
 /* ---------------------------------------------------------------------------
  * Section II: equilibrium, moments, pseudopotential.

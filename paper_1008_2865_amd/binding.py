@@ -1,0 +1,172 @@
+"""ctypes binding of liblb.so: the lb_* entry points of include/lb.h, same
+names, argument marshalling only.
+
+Every step of the method runs in the HIP library; this module converts
+Python values to C arguments and C status codes to exceptions.  Importing it
+fails loudly (``LBLibraryMissing``) when liblb.so has not been built: there is
+no fallback implementation.
+"""
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.environ.get("LB_LIBRARY", os.path.join(HERE, "liblb.so"))
+
+LB_F64, LB_F32, LB_F16DEV = 0, 1, 2
+LB_OK, LB_ERR_INVALID, LB_ERR_HIP, LB_ERR_NONFINITE, LB_ERR_STATE = 0, -1, -2, -3, -4
+STATUS_NAMES = {LB_ERR_INVALID: "LB_ERR_INVALID", LB_ERR_HIP: "LB_ERR_HIP",
+                LB_ERR_NONFINITE: "LB_ERR_NONFINITE", LB_ERR_STATE: "LB_ERR_STATE"}
+STORAGE_BYTES = {LB_F64: 8, LB_F32: 4, LB_F16DEV: 2}
+
+
+class LBLibraryMissing(ImportError):
+    pass
+
+
+class LBError(RuntimeError):
+    def __init__(self, code, message):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+class lb_params(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("log_every", ctypes.c_int32),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("trace_cap", ctypes.c_int64),
+                ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("G1", ctypes.c_double), ("G2", ctypes.c_double),
+                ("rho_ref", ctypes.c_double)]
+
+
+_vp = ctypes.c_void_p
+_P = ctypes.POINTER(lb_params)
+
+# name -> (restype, argtypes), in the order of include/lb.h
+SIGNATURES = {
+    "lb_workspace_bytes": (ctypes.c_size_t, [_P]),
+    "lb_validate": (ctypes.c_int, [_P]),
+    "lb_launch_shape": (ctypes.c_int, [_P, _vp, _vp, _vp]),
+    "lb_init": (ctypes.c_int, [ctypes.POINTER(_vp), _P, _vp, ctypes.c_size_t,
+                               _vp, _vp, _vp, ctypes.c_int, _vp]),
+    "lb_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "lb_moments": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int]),
+    "lb_pseudo_energy": (ctypes.c_int, [_vp, _vp]),
+    "lb_trace": (ctypes.c_int, [_vp, _vp, ctypes.c_int64, _vp]),
+    "lb_time": (ctypes.c_int, [_vp, _vp]),
+    "lb_get_state": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+    "lb_set_state": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_int64]),
+    "lb_tables": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp]),
+    "lb_destroy": (ctypes.c_int, [_vp]),
+    "lb_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """The loaded liblb.so (raises LBLibraryMissing if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise LBLibraryMissing(
+                f"{LIB_PATH} not found: build it with `python -m paper_1008_2865_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != LB_OK:
+        raise LBError(rc, lib().lb_last_error().decode(errors="replace"))
+    return rc
+
+
+def _ptr(a):
+    """Address of a numpy array, a torch tensor, an int or None."""
+    if a is None:
+        return None
+    if isinstance(a, int):
+        return a
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def make_params(nx, ny, *, storage=LB_F32, tau=1.0, rho0=1.0, G1=-4.9, G2=0.0,
+                log_every=0, trace_cap=0, tile_x=0, tile_y=0, rho_ref=0.0):
+    return lb_params(nx=nx, ny=ny, storage=storage, log_every=log_every,
+                     tile_x=tile_x, tile_y=tile_y, trace_cap=trace_cap, tau=tau,
+                     rho0=rho0, G1=G1, G2=G2, rho_ref=rho_ref)
+
+
+def lb_workspace_bytes(p):
+    return lib().lb_workspace_bytes(ctypes.byref(p))
+
+
+def lb_validate(p):
+    return lib().lb_validate(ctypes.byref(p))
+
+
+def lb_launch_shape(p):
+    tx, ty, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().lb_launch_shape(ctypes.byref(p), ctypes.byref(tx), ctypes.byref(ty),
+                                 ctypes.byref(nb)))
+    return tx.value, ty.value, nb.value
+
+
+def lb_init(p, workspace, nbytes, rho_init, ux_init=None, uy_init=None,
+            inputs_on_device=False, stream=0):
+    ctx = _vp()
+    _check(lib().lb_init(ctypes.byref(ctx), ctypes.byref(p), _ptr(workspace), nbytes,
+                         _ptr(rho_init), _ptr(ux_init), _ptr(uy_init),
+                         int(bool(inputs_on_device)), stream or None))
+    return ctx.value
+
+
+def lb_step(ctx, n):
+    return _check(lib().lb_step(ctx, n))
+
+
+def lb_moments(ctx, rho=None, ux=None, uy=None, on_device=False):
+    return _check(lib().lb_moments(ctx, _ptr(rho), _ptr(ux), _ptr(uy), int(bool(on_device))))
+
+
+def lb_pseudo_energy(ctx, out):
+    return _check(lib().lb_pseudo_energy(ctx, _ptr(out)))
+
+
+def lb_trace(ctx, out, cap):
+    n = ctypes.c_int64()
+    _check(lib().lb_trace(ctx, _ptr(out), cap, ctypes.byref(n)))
+    return n.value
+
+
+def lb_time(ctx):
+    t = ctypes.c_int64()
+    _check(lib().lb_time(ctx, ctypes.byref(t)))
+    return t.value
+
+
+def lb_get_state(ctx, dst, on_device=False):
+    return _check(lib().lb_get_state(ctx, _ptr(dst), int(bool(on_device))))
+
+
+def lb_set_state(ctx, src, t, on_device=False):
+    return _check(lib().lb_set_state(ctx, _ptr(src), int(bool(on_device)), t))
+
+
+def lb_tables(p, cx, cy, K, KE):
+    return _check(lib().lb_tables(ctypes.byref(p), _ptr(cx), _ptr(cy), _ptr(K), _ptr(KE)))
+
+
+def lb_destroy(ctx):
+    return _check(lib().lb_destroy(ctx))
+
+
+def lb_last_error():
+    return lib().lb_last_error().decode(errors="replace")

@@ -1,0 +1,543 @@
+// Host side of liblb.so: the C ABI declared in include/lb.h.
+//
+// Validates every argument on the host before any launch, carves the
+// caller's device workspace, keeps the time step, the ping-pong buffer
+// index and the trace bookkeeping, and issues the kernels of
+// lb_kernels.hip on the caller's stream.
+#include "lb.h"
+#include "lb_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <set>
+#include <string>
+#include <vector>
+
+using lbk::Coef;
+using lbk::Geom;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what)
+{
+    return fail(LB_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Table 1 weights p(|c|^2), the D2Q9 weights w and the first-belt rest
+// weight p_s0 = 1 - sum_k p_k = 247/420 implied by eq. (weights_1).
+constexpr double kP1 = 4.0 / 63.0, kP2 = 4.0 / 135.0, kP4 = 1.0 / 180.0,
+                 kP5 = 2.0 / 945.0, kP8 = 1.0 / 15120.0;
+constexpr double kW0 = 4.0 / 9.0, kW1 = 1.0 / 9.0, kW2 = 1.0 / 36.0;
+constexpr double kPS0 = 247.0 / 420.0;
+
+// Link order: first belt in D2Q9 order, then |c|^2 = 4, 5, 8, each
+// counter-clockwise from +x.
+constexpr int kLX[24] = {1, 0, -1, 0, 1, -1, -1, 1, 2, 0, -2, 0,
+                         2, 1, -1, -2, -2, -1, 1, 2, 2, -2, -2, 2};
+constexpr int kLY[24] = {0, 1, 0, -1, 1, 1, -1, -1, 0, 2, 0, -2,
+                         1, 2, 2, 1, -1, -2, -2, -1, 2, 2, -2, -2};
+
+double coupling(int k, double G1, double G2)
+{
+    const int c2 = kLX[k] * kLX[k] + kLY[k] * kLY[k];
+    const double p = c2 == 1 ? kP1 : c2 == 2 ? kP2 : c2 == 4 ? kP4 : c2 == 5 ? kP5 : kP8;
+    if (k < 8) return G1 * (c2 == 1 ? kW1 : kW2) + G2 * p;
+    return G2 * p;
+}
+
+Coef make_coef(const lb_params& p)
+{
+    Coef c;
+    c.K1 = coupling(0, p.G1, p.G2);
+    c.K2 = coupling(4, p.G1, p.G2);
+    c.K4 = coupling(8, p.G1, p.G2);
+    c.K5 = coupling(12, p.G1, p.G2);
+    c.K8 = coupling(20, p.G1, p.G2);
+    c.KE0 = p.G1 * kW0 + p.G2 * kPS0;
+    c.tau = p.tau;
+    c.omega = 1.0 / p.tau;
+    c.sqrt_rho0 = std::sqrt(p.rho0);
+    c.inv_rho0 = 1.0 / p.rho0;
+    c.rho_ref = p.storage == LB_F16DEV ? p.rho_ref : 0.0;
+    return c;
+}
+
+int check_params(const lb_params* p)
+{
+    if (!p) return fail(LB_ERR_INVALID, "params is NULL");
+    if (p->nx < 5 || p->ny < 5)
+        return fail(LB_ERR_INVALID, "nx, ny must be >= 5 (got %d x %d)", p->nx, p->ny);
+    if ((int64_t)p->nx * p->ny >= (int64_t(1) << 31))
+        return fail(LB_ERR_INVALID, "nx*ny must be < 2^31");
+    if (p->storage != LB_F64 && p->storage != LB_F32 && p->storage != LB_F16DEV)
+        return fail(LB_ERR_INVALID, "unknown storage %d", p->storage);
+    if (p->log_every < 0) return fail(LB_ERR_INVALID, "log_every must be >= 0");
+    if (p->trace_cap < 0) return fail(LB_ERR_INVALID, "trace_cap must be >= 0");
+    if (p->tile_x != 0 && p->tile_x != 64 && p->tile_x != 128 && p->tile_x != 256)
+        return fail(LB_ERR_INVALID, "tile_x must be 0, 64, 128 or 256 (got %d)", p->tile_x);
+    if (p->tile_y < 0 || p->tile_y > 4096)
+        return fail(LB_ERR_INVALID, "tile_y must be in [0, 4096] (got %d)", p->tile_y);
+    if (!std::isfinite(p->tau) || !(p->tau > 0.5))
+        return fail(LB_ERR_INVALID, "tau must be finite and > 0.5");
+    if (!std::isfinite(p->rho0) || !(p->rho0 > 0.0))
+        return fail(LB_ERR_INVALID, "rho0 must be finite and > 0");
+    if (!std::isfinite(p->G1) || !std::isfinite(p->G2))
+        return fail(LB_ERR_INVALID, "G1, G2 must be finite");
+    if (p->storage == LB_F16DEV && (!std::isfinite(p->rho_ref) || !(p->rho_ref > 0.0)))
+        return fail(LB_ERR_INVALID, "rho_ref must be finite and > 0 for LB_F16DEV");
+    return LB_OK;
+}
+
+// Launch shape and layout.  Defaults: the widest column strip that the
+// lattice fills, 16 rows per workgroup.
+Geom make_geom(const lb_params& p)
+{
+    Geom g;
+    g.nx = p.nx;
+    g.ny = p.ny;
+    g.pitch = (p.nx + 63) / 64 * 64;
+    g.plane = (int64_t)p.ny * g.pitch;
+    g.tile_x = p.tile_x ? p.tile_x : (p.nx >= 256 ? 256 : p.nx >= 128 ? 128 : 64);
+    g.tile_y = p.tile_y ? p.tile_y : 16;
+    if (g.tile_y > p.ny) g.tile_y = p.ny;
+    g.tiles_x = (p.nx + g.tile_x - 1) / g.tile_x;
+    g.blocks = g.tiles_x * ((p.ny + g.tile_y - 1) / g.tile_y);
+    return g;
+}
+
+// Workspace layout, each region 256-byte aligned.
+struct Layout {
+    size_t buf[2], partials, trace, scalars, staging, total;
+};
+
+Layout make_layout(const lb_params& p, const Geom& g)
+{
+    Layout L;
+    const size_t pop = align_up((size_t)9 * g.plane * lbk::storage_bytes(p.storage));
+    size_t off = 0;
+    L.buf[0] = off; off += pop;
+    L.buf[1] = off; off += pop;
+    L.partials = off; off += align_up((size_t)g.blocks * 4 * sizeof(double));
+    L.trace = off; off += align_up((size_t)p.trace_cap * 6 * sizeof(double));
+    L.scalars = off; off += align_up(8 * sizeof(double));
+    L.staging = off; off += align_up((size_t)3 * p.nx * p.ny * sizeof(double));
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+struct lb_ctx {
+    lb_params p;
+    Geom g;
+    Coef coef;
+    int device;
+    hipStream_t stream;
+    char* ws;
+    void* buf[2];
+    int cur;
+    double* partials;
+    double* trace;
+    double* scalars;
+    double* staging;
+    int64_t t;
+    int64_t trace_rows;
+    int64_t last_logged;
+};
+
+namespace {
+
+std::mutex g_mu;
+std::set<lb_ctx*> g_live;
+
+int check_ctx(lb_ctx* c)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!c || !g_live.count(c)) return fail(LB_ERR_STATE, "unknown or destroyed context");
+    return LB_OK;
+}
+
+// Makes the context's device current for the duration of a call.
+struct DeviceGuard {
+    int prev = -1;
+    hipError_t err = hipSuccess;
+    explicit DeviceGuard(int dev)
+    {
+        err = hipGetDevice(&prev);
+        if (err == hipSuccess && prev != dev) err = hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int now = -1;
+        if (prev >= 0 && hipGetDevice(&now) == hipSuccess && now != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int field_check_host(const double* v, int64_t n, bool positive, const char* name)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        if (!std::isfinite(v[i]) || (positive && !(v[i] > 0.0)))
+            return fail(LB_ERR_INVALID, "%s[%lld] = %g is not %s", name, (long long)i, v[i],
+                        positive ? "finite and > 0" : "finite");
+    }
+    return LB_OK;
+}
+
+int energy_row(lb_ctx* c, int mode, const void* src, void* dst, double* row)
+{
+    hipError_t e = lbk::launch_step(c->p.storage, mode, src, dst, c->g, c->coef, c->partials, c->stream);
+    if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+    e = lbk::launch_final(c->partials, c->g.blocks, (double)c->t, 0.5 * (c->p.G1 + c->p.G2), row,
+                          c->stream);
+    if (e != hipSuccess) return hip_fail(e, "final reduction launch");
+    return LB_OK;
+}
+
+bool rows_finite(const double* r, int64_t n)
+{
+    for (int64_t i = 0; i < n * 6; ++i)
+        if (!std::isfinite(r[i])) return false;
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+int lb_validate(const lb_params* p) { return check_params(p); }
+
+size_t lb_workspace_bytes(const lb_params* p)
+{
+    if (check_params(p) != LB_OK) return 0;
+    const Geom g = make_geom(*p);
+    return make_layout(*p, g).total;
+}
+
+int lb_launch_shape(const lb_params* p, int32_t* tile_x, int32_t* tile_y, int32_t* blocks)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    const Geom g = make_geom(*p);
+    if (tile_x) *tile_x = g.tile_x;
+    if (tile_y) *tile_y = g.tile_y;
+    if (blocks) *blocks = g.blocks;
+    return LB_OK;
+}
+
+int lb_tables(const lb_params* p, int8_t cx[24], int8_t cy[24], double K[24], double KE[25])
+{
+    if (!p) return fail(LB_ERR_INVALID, "params is NULL");
+    if (!cx || !cy || !K || !KE) return fail(LB_ERR_INVALID, "NULL output table");
+    for (int k = 0; k < 24; ++k) {
+        cx[k] = (int8_t)kLX[k];
+        cy[k] = (int8_t)kLY[k];
+        K[k] = coupling(k, p->G1, p->G2);
+        KE[1 + k] = K[k];
+    }
+    KE[0] = p->G1 * kW0 + p->G2 * kPS0;
+    return LB_OK;
+}
+
+int lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t bytes,
+            const double* rho_init, const double* ux_init, const double* uy_init,
+            int inputs_on_device, void* hip_stream)
+{
+    if (!out) return fail(LB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!workspace) return fail(LB_ERR_INVALID, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(LB_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
+    if (!rho_init) return fail(LB_ERR_INVALID, "rho_init is NULL");
+    const Geom g = make_geom(*p);
+    const Layout L = make_layout(*p, g);
+    if (bytes < L.total)
+        return fail(LB_ERR_INVALID, "workspace too small: %zu < %zu bytes", bytes, L.total);
+    const int64_t N = (int64_t)p->nx * p->ny;
+
+    // Host inputs are validated right here; device inputs after a copy back.
+    std::vector<double> host_rho;
+    if (!inputs_on_device) {
+        if ((rc = field_check_host(rho_init, N, true, "rho_init"))) return rc;
+        if (ux_init && (rc = field_check_host(ux_init, N, false, "ux_init"))) return rc;
+        if (uy_init && (rc = field_check_host(uy_init, N, false, "uy_init"))) return rc;
+    }
+
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) return fail(LB_ERR_HIP, "no HIP device available");
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+
+    if (inputs_on_device) {
+        host_rho.resize(N);
+        std::vector<double> hu;
+        if ((e = hipMemcpyAsync(host_rho.data(), rho_init, N * sizeof(double), hipMemcpyDeviceToHost, st)))
+            return hip_fail(e, "copy rho_init");
+        if ((e = hipStreamSynchronize(st))) return hip_fail(e, "synchronise");
+        if ((rc = field_check_host(host_rho.data(), N, true, "rho_init"))) return rc;
+        for (const double* u : {ux_init, uy_init}) {
+            if (!u) continue;
+            hu.resize(N);
+            if ((e = hipMemcpyAsync(hu.data(), u, N * sizeof(double), hipMemcpyDeviceToHost, st)))
+                return hip_fail(e, "copy u_init");
+            if ((e = hipStreamSynchronize(st))) return hip_fail(e, "synchronise");
+            if ((rc = field_check_host(hu.data(), N, false, u == ux_init ? "ux_init" : "uy_init")))
+                return rc;
+        }
+    }
+
+    lb_ctx* c = new lb_ctx();
+    c->p = *p;
+    c->g = g;
+    c->coef = make_coef(*p);
+    c->device = dev;
+    c->stream = st;
+    c->ws = static_cast<char*>(workspace);
+    c->buf[0] = c->ws + L.buf[0];
+    c->buf[1] = c->ws + L.buf[1];
+    c->cur = 0;
+    c->partials = reinterpret_cast<double*>(c->ws + L.partials);
+    c->trace = reinterpret_cast<double*>(c->ws + L.trace);
+    c->scalars = reinterpret_cast<double*>(c->ws + L.scalars);
+    c->staging = reinterpret_cast<double*>(c->ws + L.staging);
+    c->t = 0;
+    c->trace_rows = 0;
+    c->last_logged = -1;
+
+    const double *r = rho_init, *u = ux_init, *v = uy_init;
+    if (!inputs_on_device) {
+        double* sr = c->staging;
+        double* su = c->staging + N;
+        double* sv = c->staging + 2 * N;
+        e = hipMemcpyAsync(sr, rho_init, N * sizeof(double), hipMemcpyHostToDevice, st);
+        if (!e && ux_init) e = hipMemcpyAsync(su, ux_init, N * sizeof(double), hipMemcpyHostToDevice, st);
+        if (!e && uy_init) e = hipMemcpyAsync(sv, uy_init, N * sizeof(double), hipMemcpyHostToDevice, st);
+        if (e) {
+            delete c;
+            return hip_fail(e, "copy initial fields");
+        }
+        r = sr;
+        u = ux_init ? su : nullptr;
+        v = uy_init ? sv : nullptr;
+    }
+    if ((e = lbk::launch_init(p->storage, r, u, v, c->buf[0], g, c->coef, st)) ||
+        (e = hipStreamSynchronize(st))) {
+        delete c;
+        return hip_fail(e, "init kernel");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.insert(c);
+    }
+    *out = c;
+    return LB_OK;
+}
+
+int lb_step(lb_ctx* c, int64_t n)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (n < 0) return fail(LB_ERR_INVALID, "n must be >= 0");
+    if (n == 0) return LB_OK;
+    const int64_t le = c->p.log_every;
+    // Rows this call appends: log points in [t, t+n) not recorded yet.  The
+    // state at t+n itself is recorded by the step that leaves it (or by
+    // lb_trace), so that logging always rides on a step.
+    int64_t need = 0;
+    if (le > 0) {
+        const int64_t first = (c->t + le - 1) / le * le;
+        if (first < c->t + n) need = (c->t + n - 1 - first) / le + 1;
+        if (c->last_logged == c->t && c->t % le == 0) --need;
+    }
+    if (c->trace_rows + need > c->p.trace_cap)
+        return fail(LB_ERR_STATE, "trace full: %lld rows recorded, %lld more needed, capacity %lld",
+                    (long long)c->trace_rows, (long long)need, (long long)c->p.trace_cap);
+    DeviceGuard dg(c->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+
+    for (int64_t s = 0; s < n; ++s) {
+        const void* src = c->buf[c->cur];
+        void* dst = c->buf[c->cur ^ 1];
+        const bool log = le > 0 && c->t % le == 0 && c->last_logged != c->t;
+        if (log) {
+            if ((rc = energy_row(c, lbk::MODE_STEP_ENERGY, src, dst, c->trace + c->trace_rows * 6)))
+                return rc;
+            c->last_logged = c->t;
+            ++c->trace_rows;
+        } else {
+            hipError_t e = lbk::launch_step(c->p.storage, lbk::MODE_STEP, src, dst, c->g, c->coef,
+                                            c->partials, c->stream);
+            if (e) return hip_fail(e, "step kernel launch");
+        }
+        c->cur ^= 1;
+        ++c->t;
+    }
+    return LB_OK;
+}
+
+int lb_time(lb_ctx* c, int64_t* t)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!t) return fail(LB_ERR_INVALID, "t is NULL");
+    *t = c->t;
+    return LB_OK;
+}
+
+int lb_moments(lb_ctx* c, double* rho, double* ux, double* uy, int on_device)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    DeviceGuard dg(c->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+    const int64_t N = (int64_t)c->p.nx * c->p.ny;
+    hipError_t e;
+    if (on_device) {
+        if ((e = lbk::launch_moments(c->p.storage, c->buf[c->cur], c->g, c->coef, rho, ux, uy, c->stream)))
+            return hip_fail(e, "moments kernel");
+        return LB_OK;
+    }
+    double* s = c->staging;
+    if ((e = lbk::launch_moments(c->p.storage, c->buf[c->cur], c->g, c->coef, rho ? s : nullptr,
+                                 ux ? s + N : nullptr, uy ? s + 2 * N : nullptr, c->stream)))
+        return hip_fail(e, "moments kernel");
+    double* outs[3] = {rho, ux, uy};
+    for (int q = 0; q < 3; ++q) {
+        if (!outs[q]) continue;
+        if ((e = hipMemcpyAsync(outs[q], s + q * N, N * sizeof(double), hipMemcpyDeviceToHost, c->stream)))
+            return hip_fail(e, "copy moments");
+    }
+    if ((e = hipStreamSynchronize(c->stream))) return hip_fail(e, "synchronise");
+    return LB_OK;
+}
+
+int lb_pseudo_energy(lb_ctx* c, double out[6])
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!out) return fail(LB_ERR_INVALID, "out is NULL");
+    DeviceGuard dg(c->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+    if ((rc = energy_row(c, lbk::MODE_ENERGY, c->buf[c->cur], c->buf[c->cur ^ 1], c->scalars))) return rc;
+    hipError_t e = hipMemcpyAsync(out, c->scalars, 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (!e) e = hipStreamSynchronize(c->stream);
+    if (e) return hip_fail(e, "copy energies");
+    if (!rows_finite(out, 1)) return fail(LB_ERR_NONFINITE, "non-finite mass or energy at t = %lld", (long long)c->t);
+    return LB_OK;
+}
+
+int lb_trace(lb_ctx* c, double* out, int64_t cap, int64_t* n_rows)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (cap < 0 || (cap > 0 && !out)) return fail(LB_ERR_INVALID, "bad output buffer");
+    DeviceGuard dg(c->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+    // Record the current state first if it is a log point not yet recorded
+    // and the trace has room.
+    const int64_t le = c->p.log_every;
+    if (le > 0 && c->t % le == 0 && c->last_logged != c->t && c->trace_rows < c->p.trace_cap) {
+        if ((rc = energy_row(c, lbk::MODE_ENERGY, c->buf[c->cur], c->buf[c->cur ^ 1],
+                             c->trace + c->trace_rows * 6)))
+            return rc;
+        c->last_logged = c->t;
+        ++c->trace_rows;
+    }
+    const int64_t rows = cap < c->trace_rows ? cap : c->trace_rows;
+    hipError_t e = hipSuccess;
+    if (rows > 0)
+        e = hipMemcpyAsync(out, c->trace, rows * 6 * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (!e) e = hipStreamSynchronize(c->stream);
+    if (e) return hip_fail(e, "copy trace");
+    if (n_rows) *n_rows = c->trace_rows;
+    if (!rows_finite(out, rows)) return fail(LB_ERR_NONFINITE, "non-finite value in the trace");
+    return LB_OK;
+}
+
+int lb_get_state(lb_ctx* c, void* dst, int on_device)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!dst) return fail(LB_ERR_INVALID, "dst is NULL");
+    DeviceGuard dg(c->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+    const size_t bytes = (size_t)9 * c->p.nx * c->p.ny * lbk::storage_bytes(c->p.storage);
+    void* spare = c->buf[c->cur ^ 1];
+    hipError_t e = lbk::launch_get_state(c->p.storage, c->buf[c->cur], on_device ? dst : spare, c->g, c->stream);
+    if (e) return hip_fail(e, "state kernel");
+    if (!on_device) {
+        if ((e = hipMemcpyAsync(dst, spare, bytes, hipMemcpyDeviceToHost, c->stream)) ||
+            (e = hipStreamSynchronize(c->stream)))
+            return hip_fail(e, "copy state");
+    }
+    return LB_OK;
+}
+
+int lb_set_state(lb_ctx* c, const void* src, int on_device, int64_t t)
+{
+    int rc = check_ctx(c);
+    if (rc) return rc;
+    if (!src) return fail(LB_ERR_INVALID, "src is NULL");
+    if (t < 0) return fail(LB_ERR_INVALID, "t must be >= 0");
+    DeviceGuard dg(c->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+    const size_t bytes = (size_t)9 * c->p.nx * c->p.ny * lbk::storage_bytes(c->p.storage);
+    void* spare = c->buf[c->cur ^ 1];
+    hipError_t e = hipSuccess;
+    const void* in = src;
+    if (!on_device) {
+        if ((e = hipMemcpyAsync(spare, src, bytes, hipMemcpyHostToDevice, c->stream)))
+            return hip_fail(e, "copy state");
+        in = spare;
+    }
+    // The permutation must not read and write one buffer: when the input was
+    // staged in the spare buffer, write into the current one, else either.
+    if ((e = lbk::launch_set_state(c->p.storage, in, c->buf[c->cur], c->g, c->stream)) ||
+        (e = hipStreamSynchronize(c->stream)))
+        return hip_fail(e, "state kernel");
+    c->t = t;
+    c->last_logged = -1;
+    return LB_OK;
+}
+
+int lb_destroy(lb_ctx* c)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!c || !g_live.count(c)) return fail(LB_ERR_STATE, "unknown or destroyed context");
+        g_live.erase(c);
+    }
+    DeviceGuard dg(c->device);
+    hipError_t e = hipStreamSynchronize(c->stream);
+    delete c;
+    if (e) return hip_fail(e, "synchronise");
+    return LB_OK;
+}
+
+}  // extern "C"

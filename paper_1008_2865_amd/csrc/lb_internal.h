@@ -1,0 +1,66 @@
+// Internal interface between the C ABI (lb_api.hip) and the HIP kernels
+// (lb_kernels.hip).  Not installed; the public interface is include/lb.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace lbk {
+
+// Population storage codes (same values as enum lb_storage).
+enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16DEV = 2 };
+
+// Work done by one launch of the step kernel.
+enum Mode {
+    MODE_STEP = 0,         // stream + collide + store
+    MODE_STEP_ENERGY = 1,  // the same, plus the energy/mass block partials
+    MODE_ENERGY = 2        // energy/mass block partials only, no store
+};
+
+// Lattice geometry and launch shape.  Populations live in two buffers of
+// 9 planes each; plane i holds population i as ny rows of `pitch` elements
+// (x fastest, pitch a multiple of 64 elements), planes `plane` elements apart.
+struct Geom {
+    int32_t nx, ny;
+    int64_t pitch;    // elements per row
+    int64_t plane;    // elements per population plane
+    int32_t tile_x;   // columns per workgroup (= threads per workgroup)
+    int32_t tile_y;   // rows per workgroup
+    int32_t tiles_x;  // column strips
+    int32_t blocks;   // workgroups of the step kernel
+};
+
+// Physical coefficients, in double; the launchers convert them to the
+// arithmetic precision of the storage.
+struct Coef {
+    double K1, K2, K4, K5, K8;  // link coupling of each |c|^2 class (Table 1)
+    double KE0;                 // rest coupling of E_s: G1 w_0 + G2 p_s0
+    double tau, omega;          // BGK relaxation time and 1/tau
+    double sqrt_rho0, inv_rho0; // psi = sqrt(rho0) (1 - exp(-rho/rho0))
+    double rho_ref;             // deviation reference of ST_F16DEV
+};
+
+// Bytes of one stored population value.
+inline int storage_bytes(int storage)
+{
+    return storage == ST_F64 ? 8 : storage == ST_F32 ? 4 : 2;
+}
+
+hipError_t launch_step(int storage, int mode, const void* src, void* dst,
+                       const Geom& g, const Coef& c, double* partials,
+                       hipStream_t s);
+hipError_t launch_final(const double* partials, int blocks, double t,
+                        double half_A1, double* out_row, hipStream_t s);
+hipError_t launch_moments(int storage, const void* src, const Geom& g,
+                          const Coef& c, double* rho, double* ux, double* uy,
+                          hipStream_t s);
+hipError_t launch_init(int storage, const double* rho, const double* ux,
+                       const double* uy, void* dst, const Geom& g,
+                       const Coef& c, hipStream_t s);
+hipError_t launch_get_state(int storage, const void* src, void* dense,
+                            const Geom& g, hipStream_t s);
+hipError_t launch_set_state(int storage, const void* dense, void* dst,
+                            const Geom& g, hipStream_t s);
+
+}  // namespace lbk

@@ -1,0 +1,138 @@
+"""Host-side checks of liblb.so that need no GPU.
+
+The library loads and exports every entry point include/lb.h declares, the
+host-side validation rejects what the header says it rejects, and the link
+tables the kernels use are bit-identical to the oracle's (which are pinned to
+Table 1 in test_oracle_tables.py).
+"""
+import ctypes
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import paper_1008_2865_amd as P
+from paper_1008_2865_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "lb.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_]+)\s*\(", text)))
+
+
+def test_library_exports_every_declared_symbol():
+    names = declared_symbols()
+    assert len(names) >= 14
+    L = B.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(B.SIGNATURES), "binding and header disagree"
+
+
+def test_params_struct_layout_matches_header():
+    # int32 x6, int64, double x5 -> 72 bytes, trace_cap at 24, tau at 32.
+    assert ctypes.sizeof(B.lb_params) == 72
+    assert B.lb_params.trace_cap.offset == 24 and B.lb_params.tau.offset == 32
+
+
+def good(**kw):
+    d = dict(storage=P.LB_F32, G1=-5.444444444444445, G2=0.5444444444444445, log_every=10,
+             trace_cap=5)
+    d.update(kw)
+    return P.make_params(kw.pop("nx", 64), kw.pop("ny", 48), **{k: v for k, v in d.items()
+                                                                   if k not in ("nx", "ny")})
+
+
+@pytest.mark.parametrize("field,value", [
+    ("nx", 4), ("ny", 3), ("storage", 7), ("tau", 0.5), ("tau", float("nan")),
+    ("rho0", 0.0), ("G1", float("inf")), ("log_every", -1), ("trace_cap", -2),
+    ("tile_x", 96), ("tile_y", -1), ("tile_y", 5000)])
+def test_validation_rejects(field, value):
+    p = good()
+    setattr(p, field, value)
+    assert P.lb_validate(p) == B.LB_ERR_INVALID
+    assert P.lb_workspace_bytes(p) == 0
+    assert P.lb_last_error()
+
+
+def test_f16_needs_positive_reference():
+    p = good(storage=P.LB_F16DEV, rho_ref=0.0)
+    assert P.lb_validate(p) == B.LB_ERR_INVALID
+    p.rho_ref = 0.7
+    assert P.lb_validate(p) == B.LB_OK
+
+
+def test_workspace_and_launch_shape():
+    p = good(nx=2048, ny=2048, trace_cap=41)
+    tx, ty, nb = P.lb_launch_shape(p)
+    assert tx == 256 and ty >= 1 and nb == (2048 // tx) * math.ceil(2048 / ty)
+    # Two population buffers of 9 planes plus bookkeeping.
+    assert P.lb_workspace_bytes(p) >= 2 * 9 * 2048 * 2048 * 4
+    small = good(nx=5, ny=5)
+    assert P.lb_launch_shape(small)[0] == 64
+
+
+@pytest.mark.parametrize("G1,G2", [(-5.444444444444445, 0.5444444444444445), (1.0, 0.0), (0.0, 1.0),
+                                   (-4.9, 0.0), (-5.764705882352941, 0.8647058823529412)])
+def test_tables_bit_identical_to_oracle(G1, G2):
+    p = good(G1=G1, G2=G2)
+    cx = np.zeros(24, np.int8)
+    cy = np.zeros(24, np.int8)
+    K = np.zeros(24)
+    KE = np.zeros(25)
+    P.lb_tables(p, cx, cy, K, KE)
+    ocx, ocy, oK, oKE = O.tables(G1, G2)
+    assert np.array_equal(cx, ocx) and np.array_equal(cy, ocy)
+    assert np.array_equal(K.view(np.uint64), oK.view(np.uint64))
+    assert np.array_equal(KE.view(np.uint64), oKE.view(np.uint64))
+
+
+def test_init_rejects_bad_arguments_before_any_device_call():
+    p = good(nx=8, ny=8)
+    n = P.lb_workspace_bytes(p)
+    rho = np.full((8, 8), 0.7)
+    with pytest.raises(B.LBError) as e:
+        P.lb_init(p, 256, n - 1, rho)  # short workspace
+    assert e.value.code == B.LB_ERR_INVALID
+    with pytest.raises(B.LBError) as e:
+        P.lb_init(p, 256, n, None)
+    assert e.value.code == B.LB_ERR_INVALID
+    for bad in (np.nan, -0.1, 0.0, np.inf):
+        r = rho.copy()
+        r[3, 5] = bad
+        with pytest.raises(B.LBError) as e:
+            P.lb_init(p, 256, n, r)
+        assert e.value.code == B.LB_ERR_INVALID
+    u = np.zeros((8, 8))
+    u[0, 0] = np.nan
+    with pytest.raises(B.LBError) as e:
+        P.lb_init(p, 256, n, rho, ux_init=u)
+    assert e.value.code == B.LB_ERR_INVALID
+    with pytest.raises(B.LBError) as e:
+        P.lb_init(p, 255, n, rho)  # misaligned workspace
+    assert e.value.code == B.LB_ERR_INVALID
+
+
+def test_calls_on_unknown_context_fail_cleanly():
+    bogus = 0x1234560
+    for fn, args in [(P.lb_step, (1,)), (P.lb_time, ()), (P.lb_destroy, ()),
+                     (P.lb_pseudo_energy, (np.zeros(6),))]:
+        with pytest.raises(B.LBError) as e:
+            fn(bogus, *args)
+        assert e.value.code == B.LB_ERR_STATE
+
+
+def test_init_without_device_reports_hip_error():
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    p = good(nx=8, ny=8)
+    with pytest.raises(B.LBError) as e:
+        P.lb_init(p, 256, P.lb_workspace_bytes(p), np.full((8, 8), 0.7))
+    assert e.value.code == B.LB_ERR_HIP

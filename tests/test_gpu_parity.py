@@ -1,0 +1,262 @@
+"""GPU parity: liblb.so (HIP, gfx950) against the CPU oracle, through the C ABI.
+
+Tolerances (derived in the design notes):
+  * FP64 storage: max |d rho| <= 1e-10 after 1000 and 2000 steps of the
+    64x64 spinodal workload, energy-trace rows within 1e-11 relative;
+    full population fields within 1e-10 after 150 spinodal steps (rounding
+    differences of 1e-16 grow by ~e^(0.08 t) while the instability is
+    linear).
+  * FP32 storage: max |d rho| <= 1e-5 after 1000 steps in a stable regime;
+    in the spinodal regime the bound is three times the error of the
+    oracle's own single-precision twin (rounding is amplified by the
+    instability, so FP32 arithmetic alone produces ~4e-4 there).
+  * Fields are bit-identical across launch shapes and across repeated runs
+    (the per-site arithmetic does not depend on the tiling).
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1008_2865_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1008_2865_amd.sim import LBSim  # noqa: E402
+from paper_1008_2865_amd import binding as B  # noqa: E402
+
+R01 = inputs.couplings(0.1)
+
+
+def gpu_run(rho, steps, G1, G2, storage="f64", tau=1.0, log_every=0, chunks=None, **kw):
+    sim = LBSim(rho, G1=G1, G2=G2, tau=tau, storage=storage, log_every=log_every,
+                max_steps=steps, **kw)
+    for n in (chunks or [steps]):
+        sim.step(n)
+    return sim
+
+
+def dmax(a, b):
+    """max |a - b| as a float (keeps assertion messages short)."""
+    return float(np.max(np.abs(np.asarray(a, np.float64) - np.asarray(b, np.float64))))
+
+
+def oracle_f(rho, steps, G1, G2, tau=1.0, precision="f64"):
+    return O.step(O.init(rho, precision=precision), steps, tau, 1.0, G1, G2, precision=precision)
+
+
+# ---------------------------------------------------------------------------
+# FP64, the 64x64 spinodal workload (r = 0.1, seed 1, energy every 50 steps).
+# ---------------------------------------------------------------------------
+def test_f64_workload_fields_and_trace():
+    rho0 = inputs.rho_noise(64, 64, 1)
+    G1, G2 = R01
+    f1000, tr_o = O.run(O.init(rho0), 1000, 1.0, 1.0, G1, G2, 50)
+    f2000, tr_o2 = O.run(f1000, 1000, 1.0, 1.0, G1, G2, 50)
+    sim = gpu_run(rho0, 2000, G1, G2, log_every=50, chunks=[1000])
+    rho_g, _, _ = sim.moments()
+    assert dmax(rho_g, f1000.sum(axis=0)) <= 1e-10
+    sim.step(1000)
+    rho_g, _, _ = sim.moments()
+    assert dmax(rho_g, f2000.sum(axis=0)) <= 1e-10
+    tr = sim.trace()
+    ref = np.concatenate([tr_o, tr_o2[1:]])
+    assert tr.shape == (41, 6) and np.array_equal(tr[:, 0], np.arange(0, 2001, 50))
+    rel = np.abs(tr[:, 1:] - ref[:, 1:]) / np.abs(ref[:, 1:])
+    assert rel.max() <= 1e-11, rel.max(axis=0)
+    sim.close()
+
+
+@pytest.mark.parametrize("nx,ny,tile_x,tile_y", [
+    (100, 70, 64, 16),     # ragged in x and y
+    (130, 37, 128, 5),
+    (300, 90, 256, 64),
+    (5, 5, 64, 1),          # smallest lattice: every link wraps
+    (7, 5, 64, 3),
+    (5, 9, 64, 16),
+    (257, 11, 256, 4)])
+def test_f64_populations_match_oracle(nx, ny, tile_x, tile_y):
+    G1, G2 = R01
+    rho0 = inputs.rho_noise(nx, ny, 3)
+    steps = 150
+    fo = oracle_f(rho0, steps, G1, G2, tau=0.8)
+    sim = gpu_run(rho0, steps, G1, G2, tau=0.8, tile_x=tile_x, tile_y=tile_y)
+    fg = sim.get_state()
+    assert dmax(fg, fo) <= 1e-10
+    sim.close()
+
+
+def test_fields_bit_identical_across_launch_shapes():
+    G1, G2 = R01
+    rho0 = inputs.rho_noise(300, 90, 4)
+    states = []
+    for tx, ty in [(64, 1), (64, 16), (128, 7), (256, 64), (256, 90)]:
+        sim = gpu_run(rho0, 60, G1, G2, storage="f32", tile_x=tx, tile_y=ty)
+        states.append(sim.get_state())
+        sim.close()
+    for s in states[1:]:
+        assert np.array_equal(s.view(np.uint32), states[0].view(np.uint32))
+
+
+def test_velocity_and_energy_match_oracle():
+    G1, G2 = R01
+    rng = np.random.default_rng(8)
+    rho0 = inputs.rho_noise(48, 40, 8)
+    ux = rng.uniform(-0.02, 0.02, rho0.shape)
+    uy = rng.uniform(-0.02, 0.02, rho0.shape)
+    fo = O.step(O.init(rho0, ux, uy), 77, 1.1, 1.0, G1, G2)
+    sim = LBSim(rho0, G1=G1, G2=G2, tau=1.1, storage="f64", ux_init=ux, uy_init=uy)
+    sim.step(77)
+    rho, vx, vy = sim.moments()
+    r_o = fo.sum(axis=0)
+    cx = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+    cy = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
+    assert dmax(rho, r_o) <= 1e-12
+    assert dmax(vx, np.tensordot(cx, fo, axes=1) / r_o) <= 1e-12
+    assert dmax(vy, np.tensordot(cy, fo, axes=1) / r_o) <= 1e-12
+    e = sim.pseudo_energy()
+    eo = O.observables(fo, 1.0, G1, G2)
+    assert e[0] == 77
+    assert np.all(np.abs(e[1:] - eo) <= 1e-12 * np.abs(eo))
+    # Device-side outputs equal the host copies.
+    d = sim.moments(device=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(d[0].cpu().numpy(), rho) and np.array_equal(d[2].cpu().numpy(), vy)
+    sim.close()
+
+
+# ---------------------------------------------------------------------------
+# FP32 storage.
+# ---------------------------------------------------------------------------
+def test_f32_stable_regime_1000_steps():
+    G1, G2 = inputs.couplings(0.1, -3.0)  # A1 = -3: above the critical -4
+    rho0 = inputs.rho_noise(64, 64, 1)
+    fo = oracle_f(rho0, 1000, G1, G2)
+    sim = gpu_run(rho0, 1000, G1, G2, storage="f32")
+    rho, _, _ = sim.moments()
+    assert dmax(rho, fo.sum(axis=0)) <= 1e-5
+    sim.close()
+
+
+def test_f32_spinodal_regime_against_twin_error():
+    G1, G2 = R01
+    rho0 = inputs.rho_noise(64, 64, 1)
+    fo, tr_o = O.run(O.init(rho0), 1000, 1.0, 1.0, G1, G2, 100)
+    ft = oracle_f(rho0, 1000, G1, G2, precision="f32")
+    twin = np.max(np.abs(ft.sum(axis=0).astype(np.float64) - fo.sum(axis=0)))
+    sim = gpu_run(rho0, 1000, G1, G2, storage="f32", log_every=100)
+    rho, _, _ = sim.moments()
+    err = np.max(np.abs(rho - fo.sum(axis=0)))
+    assert err <= max(3 * twin, 1e-5), (err, twin)
+    tr = sim.trace()
+    E, Eo = tr[:, 2] + tr[:, 3], tr_o[:, 2] + tr_o[:, 3]
+    rel_e = float(np.max(np.abs(E - Eo) / np.abs(Eo)))
+    assert rel_e <= 1e-4
+    # The rest population is taken from exact mass conservation: the FP32
+    # mass drift stays at the level of the FP64 reduction of FP32 values.
+    assert np.max(np.abs(tr[:, 1] - tr[0, 1])) / tr[0, 1] <= 1e-6
+    sim.close()
+
+
+def test_f32_full_size_launch_configuration():
+    # 2048x2048, the benchmark's launch shape: a few steps against the oracle.
+    G1, G2 = R01
+    rho0 = inputs.rho_noise(2048, 2048, 1)
+    fo = oracle_f(rho0, 5, G1, G2)
+    sim = gpu_run(rho0, 5, G1, G2, storage="f32", log_every=5)
+    rho, _, _ = sim.moments()
+    assert dmax(rho, fo.sum(axis=0)) <= 2e-6
+    tr = sim.trace()
+    eo = O.observables(fo, 1.0, G1, G2)
+    assert tr.shape[0] == 2 and tr[1, 0] == 5
+    assert np.all(np.abs(tr[1, 1:] - eo) <= 1e-5 * np.abs(eo))
+    sim.close()
+
+
+# ---------------------------------------------------------------------------
+# Determinism, chunking, checkpoint/restore.
+# ---------------------------------------------------------------------------
+def test_runs_are_bit_reproducible_and_chunk_independent():
+    G1, G2 = R01
+    rho0 = inputs.rho_noise(128, 96, 5)
+    a = gpu_run(rho0, 300, G1, G2, storage="f32", log_every=25)
+    b = gpu_run(rho0, 300, G1, G2, storage="f32", log_every=25, chunks=[1] * 7 + [93, 50, 150])
+    sa, sb = a.get_state(), b.get_state()
+    assert np.array_equal(sa.view(np.uint32), sb.view(np.uint32))
+    ta, tb = a.trace(), b.trace()
+    assert ta.shape == tb.shape == (13, 6)
+    assert np.array_equal(ta, tb)
+    a.close()
+    b.close()
+
+
+def test_checkpoint_restore_is_exact():
+    G1, G2 = R01
+    rho0 = inputs.rho_noise(96, 64, 6)
+    ref = gpu_run(rho0, 400, G1, G2, storage="f32")
+    mid = gpu_run(rho0, 150, G1, G2, storage="f32")
+    ck = mid.get_state()
+    fresh = LBSim(np.full((64, 96), 0.5), G1=G1, G2=G2, storage="f32")
+    fresh.set_state(ck, 150)
+    assert fresh.t == 150
+    assert np.array_equal(fresh.get_state().view(np.uint32), ck.view(np.uint32))
+    fresh.step(250)
+    assert np.array_equal(fresh.get_state().view(np.uint32), ref.get_state().view(np.uint32))
+    for s in (ref, mid, fresh):
+        s.close()
+
+
+# ---------------------------------------------------------------------------
+# Half-precision deviation storage (stated error, not bit parity).
+# ---------------------------------------------------------------------------
+def test_f16dev_error_is_bounded():
+    G1, G2 = inputs.couplings(0.1, -3.0)
+    rho0 = inputs.rho_noise(64, 64, 1)
+    fo = oracle_f(rho0, 200, G1, G2)
+    sim = gpu_run(rho0, 200, G1, G2, storage="f16dev")
+    rho, _, _ = sim.moments()
+    assert dmax(rho, fo.sum(axis=0)) <= 2e-3
+    sim.close()
+
+
+# ---------------------------------------------------------------------------
+# Failure paths (forced from the host; every kernel exits normally).
+# ---------------------------------------------------------------------------
+def test_trace_overflow_leaves_state_untouched():
+    G1, G2 = R01
+    sim = LBSim(inputs.rho_noise(32, 32, 2), G1=G1, G2=G2, storage="f32", log_every=10,
+                trace_cap=3)
+    sim.step(20)
+    assert np.array_equal(sim.trace()[:, 0], [0, 10, 20])  # t = 20 recorded on read
+    sim.step(10)  # t = 20 is already recorded: no new row needed
+    with pytest.raises(B.LBError) as e:
+        sim.step(5)  # would need a row for t = 30
+    assert e.value.code == B.LB_ERR_STATE and sim.t == 30
+    assert sim.trace().shape == (3, 6)  # no room: t = 30 is not recorded
+    sim.close()
+
+
+def test_destroyed_context_is_rejected():
+    G1, G2 = R01
+    sim = LBSim(inputs.rho_noise(16, 16, 2), G1=G1, G2=G2, storage="f32")
+    ctx = sim.ctx
+    sim.close()
+    with pytest.raises(B.LBError) as e:
+        B.lb_step(ctx, 1)
+    assert e.value.code == B.LB_ERR_STATE
+
+
+def test_device_inputs_are_validated():
+    G1, G2 = R01
+    rho = torch.full((16, 16), 0.7, dtype=torch.float64, device="cuda")
+    rho[3, 3] = float("nan")
+    with pytest.raises(B.LBError) as e:
+        LBSim(rho, G1=G1, G2=G2, storage="f32")
+    assert e.value.code == B.LB_ERR_INVALID
+    rho[3, 3] = 0.7
+    sim = LBSim(rho, G1=G1, G2=G2, storage="f32")
+    sim.step(3)
+    sim.close()

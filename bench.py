@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--log-every", type=int, default=500)
     ap.add_argument("--tile-x", type=int, default=0)
     ap.add_argument("--tile-y", type=int, default=0)
+    ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="oracle sample length; 0 skips the CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=None)
@@ -119,9 +120,10 @@ def main():
     rho0 = inputs.rho_noise(n, n, args.seed)
     total = W + K
     sim = LBSim(rho0, G1=G1, G2=G2, storage=args.storage, log_every=le,
-                max_steps=total + le, tile_x=args.tile_x, tile_y=args.tile_y)
-    tx, ty, nb = sim.launch_shape()
-    log(f"bench: {n}x{n} {args.storage}, r={args.r}, tile {tx}x{ty}, {nb} workgroups, "
+                max_steps=total + le, tile_x=args.tile_x, tile_y=args.tile_y,
+                tile_rows=args.tile_rows)
+    tx, ty, tr, nb = sim.launch_shape()
+    log(f"bench: {n}x{n} {args.storage}, r={args.r}, tile {tx}x{ty}x{tr}, {nb} workgroups, "
         f"warmup {W}, steps {K}, log every {le}")
     moments = [torch.empty((n, n), dtype=torch.float64, device="cuda") for _ in range(3)]
 
@@ -158,10 +160,10 @@ def main():
     region_s = e0.elapsed_time(e1) / 1e3
     step_s = sum(a.elapsed_time(b) for a, b, _ in pairs) / 1e3
     launches = sum(c for _, _, c in pairs)
-    tr = sim.trace()
+    trace = sim.trace()
     log(f"bench: region {region_s * 1e3:.2f} ms (host wall {wall * 1e3:.2f} ms), "
         f"step kernels {step_s * 1e3:.2f} ms over {launches} launches; "
-        f"trace rows {len(tr)}, last E = {tr[-1, 2] + tr[-1, 3]:.6g}")
+        f"trace rows {len(trace)}, last E = {trace[-1, 2] + trace[-1, 3]:.6g}")
 
     if args.copy_calib:
         nbytes = 9 * n * n * 4
@@ -177,7 +179,7 @@ def main():
     value = sites * K / region_s / 1e6
     avg_launch = step_s / launches
     achieved = bpl * sites / avg_launch / 1e9
-    workload_key = f"{n}x{n} {args.storage} r={args.r} tile {tx}x{ty}"
+    workload_key = f"{n}x{n} {args.storage} r={args.r} tile {tx}x{ty}x{tr}"
     traffic = measured_traffic(workload_key)
     out = {
         "metric": METRIC,
@@ -197,7 +199,7 @@ def main():
                         f"A1=-4.9, G2/|G1|={args.r}, tau=1, rho0=1, rho=0.7(1+0.01U) seed {args.seed}, "
                         f"moments + pseudo-energy every {le} steps",
             "nx": n, "ny": n, "storage": args.storage, "G1": G1, "G2": G2, "tau": 1.0,
-            "log_every": le, "tile_x": tx, "tile_y": ty, "workgroups": nb,
+            "log_every": le, "tile_x": tx, "tile_y": ty, "tile_rows": tr, "workgroups": nb,
         },
         "effective_gbps": round(value * bpl / 1e3, 1),
         "roofline": {

@@ -72,6 +72,9 @@ typedef struct lb_params {
     int32_t tile_x;      /* columns per workgroup: 0 (library choice), 64, 128
                             or 256                                               */
     int32_t tile_y;      /* rows per workgroup: 0 (library choice) or 1..4096    */
+    int32_t tile_rows;   /* rows a workgroup updates per pipeline stage:
+                            0 (library choice), 1 or 2                           */
+    int32_t reserved;    /* must be 0                                            */
     int64_t trace_cap;   /* rows the trace can hold (>= 0)                       */
     double tau;          /* BGK relaxation time, > 0.5 (the paper uses 1)        */
     double rho0;         /* psi scale, > 0 (the paper fixes rho0 = 1)            */
@@ -88,9 +91,10 @@ size_t lb_workspace_bytes(const lb_params* p);
 int lb_validate(const lb_params* p);
 
 /* Resolved launch shape for these parameters: columns and rows per
- * workgroup and the workgroup count of the step kernel (host only). */
+ * workgroup, rows per pipeline stage and the workgroup count of the step
+ * kernel (host only).  Any output may be NULL. */
 int lb_launch_shape(const lb_params* p, int32_t* tile_x, int32_t* tile_y,
-                    int32_t* blocks);
+                    int32_t* tile_rows, int32_t* blocks);
 
 /* Create a context at t = 0 whose populations are the equilibrium
  * f_i^eq(rho_init, u_init) of section II (the paper starts from a fluid at

@@ -98,6 +98,9 @@ int check_params(const lb_params* p)
         return fail(LB_ERR_INVALID, "tile_x must be 0, 64, 128 or 256 (got %d)", p->tile_x);
     if (p->tile_y < 0 || p->tile_y > 4096)
         return fail(LB_ERR_INVALID, "tile_y must be in [0, 4096] (got %d)", p->tile_y);
+    if (p->tile_rows < 0 || p->tile_rows > 2)
+        return fail(LB_ERR_INVALID, "tile_rows must be 0, 1 or 2 (got %d)", p->tile_rows);
+    if (p->reserved != 0) return fail(LB_ERR_INVALID, "reserved must be 0");
     if (!std::isfinite(p->tau) || !(p->tau > 0.5))
         return fail(LB_ERR_INVALID, "tau must be finite and > 0.5");
     if (!std::isfinite(p->rho0) || !(p->rho0 > 0.0))
@@ -116,11 +119,17 @@ Geom make_geom(const lb_params& p)
     Geom g;
     g.nx = p.nx;
     g.ny = p.ny;
+    // Row pitch: a multiple of 64 elements whose count of 64-element blocks
+    // is odd, so consecutive rows (and the rows that concurrently running
+    // workgroups touch) do not sit at power-of-two strides, which would
+    // pile their accesses onto the same HBM channels.
     g.pitch = (p.nx + 63) / 64 * 64;
+    if ((g.pitch / 64) % 2 == 0) g.pitch += 64;
     g.plane = (int64_t)p.ny * g.pitch;
     g.tile_x = p.tile_x ? p.tile_x : (p.nx >= 256 ? 256 : p.nx >= 128 ? 128 : 64);
-    g.tile_y = p.tile_y ? p.tile_y : 16;
+    g.tile_y = p.tile_y ? p.tile_y : 32;
     if (g.tile_y > p.ny) g.tile_y = p.ny;
+    g.rows_per_iter = p.tile_rows ? p.tile_rows : 1;
     g.tiles_x = (p.nx + g.tile_x - 1) / g.tile_x;
     g.blocks = g.tiles_x * ((p.ny + g.tile_y - 1) / g.tile_y);
     return g;
@@ -236,13 +245,15 @@ size_t lb_workspace_bytes(const lb_params* p)
     return make_layout(*p, g).total;
 }
 
-int lb_launch_shape(const lb_params* p, int32_t* tile_x, int32_t* tile_y, int32_t* blocks)
+int lb_launch_shape(const lb_params* p, int32_t* tile_x, int32_t* tile_y, int32_t* tile_rows,
+                    int32_t* blocks)
 {
     int rc = check_params(p);
     if (rc) return rc;
     const Geom g = make_geom(*p);
     if (tile_x) *tile_x = g.tile_x;
     if (tile_y) *tile_y = g.tile_y;
+    if (tile_rows) *tile_rows = g.rows_per_iter;
     if (blocks) *blocks = g.blocks;
     return LB_OK;
 }

@@ -29,6 +29,7 @@ struct Geom {
     int32_t tile_y;   // rows per workgroup
     int32_t tiles_x;  // column strips
     int32_t blocks;   // workgroups of the step kernel
+    int32_t rows_per_iter;  // rows each workgroup updates per pipeline stage (1 or 2)
 };
 
 // Physical coefficients, in double; the launchers convert them to the

@@ -24,6 +24,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 namespace lbk {
 namespace {
 
@@ -154,7 +156,32 @@ __device__ __forceinline__ double wave_sum(double v)
 // ---------------------------------------------------------------------------
 // The fused step.  Threads = tile_x = NT; LDS ring of 6 psi rows of NT + 4.
 // ---------------------------------------------------------------------------
-template <class P, int NT, int MODE>
+
+// D2Q9 speed components, population order (0,0) (1,0) (0,1) (-1,0) (0,-1)
+// (1,1) (-1,1) (-1,-1) (1,-1), packed two bits per population as c + 1 so a
+// lane can look up its own population's speed without a memory table.
+constexpr int kQCx[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+constexpr int kQCy[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+constexpr unsigned pack_speeds(const int* c)
+{
+    unsigned v = 0;
+    for (int i = 0; i < 9; ++i) v |= (unsigned)(c[i] + 1) << (2 * i);
+    return v;
+}
+constexpr unsigned kCxPack = pack_speeds(kQCx);
+constexpr unsigned kCyPack = pack_speeds(kQCy);
+__device__ __forceinline__ int q_cx(int i) { return (int)((kCxPack >> (2 * i)) & 3u) - 1; }
+__device__ __forceinline__ int q_cy(int i) { return (int)((kCyPack >> (2 * i)) & 3u) - 1; }
+static_assert(((kCxPack >> 0) & 3u) == 1u && ((kCxPack >> 6) & 3u) == 0u &&
+                  ((kCyPack >> 8) & 3u) == 0u && ((kCyPack >> 10) & 3u) == 2u,
+              "speed packing");
+
+template <int J>
+using Ic = std::integral_constant<int, J>;
+
+// One launch = one time step for a tile of NT columns (one lane each) by
+// tile_y rows, walked RPI rows at a time.
+template <class P, int NT, int MODE, int RPI>
 __global__ void __launch_bounds__(NT)
 k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
        Geom g, CoefT<typename P::C> k, double* __restrict__ partials)
@@ -164,16 +191,37 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
     constexpr bool kEnergy = MODE != MODE_STEP;
     constexpr bool kCollide = MODE != MODE_ENERGY;
     constexpr int LW = NT + 4;
-    __shared__ C ring[6][LW];
+    constexpr int kWaves = NT / 64;
+    constexpr int kHpw = 4 / kWaves;  // halo columns gathered per wave
+    // psi ring: walk rows -2 .. RPI+1 around the rows being updated, plus
+    // RPI rows being staged.  Population buffers: the RPI rows being
+    // updated, the 2 rows after them (psi staged) and RPI lead rows whose
+    // loads are in flight.
+    constexpr int RS = 4 + 2 * RPI;
+    constexpr int NB = 2 + 2 * RPI;
+    constexpr int U = NB / RPI;
+    static_assert(NB % RPI == 0, "buffer rotation must be a whole number of iterations");
+    __shared__ C ring[RS][LW];
 
     const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
     const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int sx = lb % g.tiles_x;
     const int sy = lb / g.tiles_x;
     const int x0 = sx * NT;
     const int y0 = sy * g.tile_y;
     const int y1 = min(y0 + g.tile_y, g.ny);
-    const int nx = g.nx;
+    // Vertically adjacent tiles walk in opposite directions, so the rows
+    // at a shared tile boundary are pulled by both tiles at about the same
+    // time (both at the start or both at the end of their walk) and the
+    // second pull of those halo rows is served by L2.
+    const int dir = (sy & 1) ? -1 : 1;
+    const int ystart = dir > 0 ? y0 : y1 - 1;
+    const int nrows = y1 - y0;
+    const int nx = g.nx, ny = g.ny;
+    // Lattice row of walk row r (r may run up to 2 rows past either end).
+    auto wrow = [&](int r) { return wrapi(ystart + r * dir, ny); };
 
     const S* pl[9];
     S* pd[9];
@@ -184,150 +232,238 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
     }
     const Offs<P> o(k.rho_ref);
 
-    // This lane's column (LDS column tid + 2) ...
+    // This lane's column, LDS column tid + 2.
     const bool own = x0 + tid < nx;
     const int xc = (x0 + tid) % nx;
     const int xcm = xc == 0 ? nx - 1 : xc - 1;
     const int xcp = xc == nx - 1 ? 0 : xc + 1;
-    // ... and, for lanes 0..3, one halo column: LDS 0, 1, NT+2, NT+3.
-    const bool halo = tid < 4;
-    const int hc = tid < 2 ? tid : NT + tid;
-    int hx = (x0 - 2 + hc) % nx;
-    hx = hx < 0 ? hx + nx : hx;
-    const int hxm = hx == 0 ? nx - 1 : hx - 1;
-    const int hxp = hx == nx - 1 ? 0 : hx + 1;
 
-    C R0[9], R1[9], L[9];
+    // Halo: the 4 columns x0-2, x0-1, x0+NT, x0+NT+1 (LDS 0, 1, NT+2, NT+3).
+    // Each wave gathers kHpw of them with a single load instruction per row:
+    // lane j < 9 kHpw fetches population j % 9 of halo column j / 9 (the
+    // other lanes repeat the last address), and the nine values are then
+    // summed across lanes.  No lane-divergent loads.
+    const int hj = lane < 9 * kHpw ? lane : 9 * kHpw - 1;
+    const int hi = hj % 9;
+    const int hcol = wid * kHpw + hj / 9;
+    const int hlds = hcol < 2 ? hcol : NT + hcol;
+    int hgx = (x0 - 2 + hlds - q_cx(hi)) % nx;
+    hgx = hgx < 0 ? hgx + nx : hgx;
+    const S* hp = src + (int64_t)hi * g.plane + hgx;
+    const int hcy = q_cy(hi);
+    const C hoff = o.of(hi);
+    const int mcol = wid * kHpw + (lane < kHpw ? lane : 0);
+    const int mlds = mcol < 2 ? mcol : NT + mcol;
+    const int gbase = 9 * (lane < kHpw ? lane : 0);
 
-    // Prologue: psi of rows y0-2 .. y0+1 into ring slots 0..3; keep the
-    // populations of rows y0 and y0+1.
-#pragma unroll 1
-    for (int j = -2; j < 2; ++j) {
-        const int y = wrapi(y0 + j, g.ny);
-        pull<P>(pl, g, xc, xcm, xcp, y, o, L);
-        ring[j + 2][tid + 2] = psi_of(density(L), k);
-        if (halo) {
-            C h[9];
-            pull<P>(pl, g, hx, hxm, hxp, y, o, h);
-            ring[j + 2][hc] = psi_of(density(h), k);
-        }
-        if (j == 0) {
+    auto halo_load = [&](int y) -> C {
+        // Row y - c_y of this lane's population, from the three row offsets
+        // every lane of the wave shares.
+        const int ym = y == 0 ? ny - 1 : y - 1;
+        const int yp = y == ny - 1 ? 0 : y + 1;
+        const int64_t r = hcy > 0 ? (int64_t)ym * g.pitch
+                                  : (hcy < 0 ? (int64_t)yp * g.pitch : (int64_t)y * g.pitch);
+        return P::ld(hp + r, hoff);
+    };
+    auto halo_psi = [&](C hv, int slot) {
+        C h[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) R0[i] = L[i];
-        } else if (j == 1) {
+        for (int m = 0; m < 9; ++m) h[m] = __shfl(hv, gbase + m, 64);
+        const C ps = psi_of(density(h), k);
+        if (lane < kHpw) ring[slot][mlds] = ps;
+    };
+
+    // Walk row r lives in buffer r % NB.  Each loop iteration advances RPI
+    // rows and the loop body is unrolled U = NB / RPI times, so every
+    // buffer index below is a compile-time constant: the rotation is a
+    // renaming, never a register copy (a copy of a register whose load may
+    // still be outstanding would force a wait on the memory counter, which
+    // on this target also counts the stores just issued).
+    C Bf[NB][9] = {};
+
+    // Prologue: psi of walk rows -2 .. RPI+1 into ring slots 0 .. RPI+3 and
+    // the populations of rows 0 .. RPI+1 into Bf[0 .. RPI+1].  All rows are
+    // requested before any is used, so the prologue costs one latency.
+    {
+        C T0[9], T1[9], hv[RPI + 4];
+        pull<P>(pl, g, xc, xcm, xcp, wrow(-2), o, T0);
+        pull<P>(pl, g, xc, xcm, xcp, wrow(-1), o, T1);
 #pragma unroll
-            for (int i = 0; i < 9; ++i) R1[i] = L[i];
-        }
+        for (int r = 0; r < RPI + 2; ++r) pull<P>(pl, g, xc, xcm, xcp, wrow(r), o, Bf[r]);
+#pragma unroll
+        for (int r = -2; r < RPI + 2; ++r) hv[r + 2] = halo_load(wrow(r));
+        ring[0][tid + 2] = psi_of(density(T0), k);
+        ring[1][tid + 2] = psi_of(density(T1), k);
+#pragma unroll
+        for (int r = 0; r < RPI + 2; ++r) ring[r + 2][tid + 2] = psi_of(density(Bf[r]), k);
+#pragma unroll
+        for (int r = 0; r < RPI + 4; ++r) halo_psi(hv[r], r);
     }
 
     double aM = 0.0, aEs = 0.0, aEm = 0.0, aS2 = 0.0;
-    int s0 = 0;  // ring slot of row y - 2
 
-#pragma unroll 1
-    for (int y = y0; y < y1; ++y) {
-        // Lead row y + 2 into slot s0 + 4.
-        const int yl = wrapi(y + 2, g.ny);
-        const int sl = s0 + 4 >= 6 ? s0 - 2 : s0 + 4;
-        pull<P>(pl, g, xc, xcm, xcp, yl, o, L);
-        ring[sl][tid + 2] = psi_of(density(L), k);
-        if (halo) {
-            C h[9];
-            pull<P>(pl, g, hx, hxm, hxp, yl, o, h);
-            ring[sl][hc] = psi_of(density(h), k);
+    // Software pipeline, per iteration (rows b .. b+RPI-1 along the walk):
+    //   issue the loads of the lead rows b+RPI+2 .. b+2RPI+1 | barrier |
+    //   force + collision of rows b .. b+RPI-1 | psi of the lead rows into
+    //   the ring slots of rows b-RPI-2 .. b-3 | stores.
+    // The loads overlap the barrier and the arithmetic; the stores overlap
+    // the next iteration's barrier and arithmetic.  The overwritten slots
+    // were last read in the previous iteration, before this barrier.  Lead
+    // rows past the end of the walk re-read row b instead (an L2 hit), so
+    // no load is conditional.
+    auto group = [&](auto Jc, int it, int s0) {
+        constexpr int J = decltype(Jc)::value;
+        const int b = it * RPI;
+        C hvl[RPI];
+#pragma unroll
+        for (int m = 0; m < RPI; ++m) {
+            const int r = b + RPI + 2 + m;
+            const int yl = r < nrows + 2 ? wrow(r) : wrow(b);
+            pull<P>(pl, g, xc, xcm, xcp, yl, o, Bf[(J * RPI + RPI + 2 + m) % NB]);
+            hvl[m] = halo_load(yl);
         }
         __syncthreads();
 
-        const int s1 = s0 + 1 >= 6 ? s0 - 5 : s0 + 1;
-        const int s2 = s0 + 2 >= 6 ? s0 - 4 : s0 + 2;
-        const int s3 = s0 + 3 >= 6 ? s0 - 3 : s0 + 3;
-        const C* rm2 = ring[s0];
-        const C* rm1 = ring[s1];
-        const C* rc = ring[s2];
-        const C* rp1 = ring[s3];
-        const C* rp2 = ring[sl];
-        const int c = tid + 2;
-
-        const C p = rc[c];
-        // psi(x + dx, y + dy), named by direction.
-        const C e1 = rc[c + 1], w1 = rc[c - 1], n1 = rp1[c], s1v = rm1[c];
-        const C ne = rp1[c + 1], nw = rp1[c - 1], sw = rm1[c - 1], se = rm1[c + 1];
-        const C e2 = rc[c + 2], w2 = rc[c - 2], n2 = rp2[c], s2v = rm2[c];
-        const C e2n = rp1[c + 2], e2s = rm1[c + 2], w2n = rp1[c - 2], w2s = rm1[c - 2];
-        const C n2e = rp2[c + 1], n2w = rp2[c - 1], s2e = rm2[c + 1], s2w = rm2[c - 1];
-        const C ne2 = rp2[c + 2], nw2 = rp2[c - 2], sw2 = rm2[c - 2], se2 = rm2[c + 2];
-
-        if (kEnergy && own) {
-            const C S1 = (e1 + w1) + (n1 + s1v);
-            const C S2 = (ne + sw) + (nw + se);
-            const C S4 = (e2 + w2) + (n2 + s2v);
-            const C S5 = ((e2n + w2s) + (e2s + w2n)) + ((n2e + s2w) + (n2w + s2e));
-            const C S8 = (ne2 + sw2) + (nw2 + se2);
-            const C es = (C)0.5 * p * (k.KE0 * p + k.K1 * S1 + k.K2 * S2);
-            const C em = (C)0.5 * p * (k.K4 * S4 + k.K5 * S5 + k.K8 * S8);
-            aM += (double)density(R0);
-            aEs += (double)es;
-            aEm += (double)em;
-            aS2 += (double)p * (double)p;
-        }
-
-        if (kCollide) {
-            // eq. (FORCE): F = -psi(x) sum_k K_k psi(x + c_k) c_k, links
-            // paired with their opposites.
-            const C sumx = k.K1 * (e1 - w1) + k.K2 * ((ne + se) - (nw + sw)) +
-                           (C)2 * k.K4 * (e2 - w2) +
-                           k.K5 * ((C)2 * ((e2n + e2s) - (w2n + w2s)) + ((n2e + s2e) - (n2w + s2w))) +
-                           (C)2 * k.K8 * ((ne2 + se2) - (nw2 + sw2));
-            const C sumy = k.K1 * (n1 - s1v) + k.K2 * ((ne + nw) - (se + sw)) +
-                           (C)2 * k.K4 * (n2 - s2v) +
-                           k.K5 * ((C)2 * ((n2e + n2w) - (s2e + s2w)) + ((e2n + w2n) - (e2s + w2s))) +
-                           (C)2 * k.K8 * ((ne2 + nw2) - (se2 + sw2));
-            const C Fx = -p * sumx;
-            const C Fy = -p * sumy;
-
-            // BGK collision at u_eq = (j + tau F) / rho.
-            const C rho = density(R0);
-            const C jx = (R0[1] - R0[3]) + ((R0[5] - R0[7]) + (R0[8] - R0[6]));
-            const C jy = (R0[2] - R0[4]) + ((R0[5] - R0[7]) + (R0[6] - R0[8]));
-            const C inv = (C)1 / rho;
-            const C ux = (jx + k.tau * Fx) * inv;
-            const C uy = (jy + k.tau * Fy) * inv;
-            const C usq = (C)1.5 * (ux * ux + uy * uy);
-            const C r1 = rho * ((C)1 / (C)9);
-            const C r2 = rho * ((C)1 / (C)36);
-            const C om = k.omega;
-            C q[9];
-            auto axis = [&](C cu) { return r1 * ((C)1 + (C)3 * cu + (C)4.5 * cu * cu - usq); };
-            auto diag = [&](C cu) { return r2 * ((C)1 + (C)3 * cu + (C)4.5 * cu * cu - usq); };
-            q[1] = R0[1] + om * (axis(ux) - R0[1]);
-            q[2] = R0[2] + om * (axis(uy) - R0[2]);
-            q[3] = R0[3] + om * (axis(-ux) - R0[3]);
-            q[4] = R0[4] + om * (axis(-uy) - R0[4]);
-            q[5] = R0[5] + om * (diag(ux + uy) - R0[5]);
-            q[6] = R0[6] + om * (diag(uy - ux) - R0[6]);
-            q[7] = R0[7] + om * (diag(-ux - uy) - R0[7]);
-            q[8] = R0[8] + om * (diag(ux - uy) - R0[8]);
-            // The collision conserves mass exactly; take the rest
-            // population from that so rounding cannot drift the mass.
-            q[0] = rho - (((q[1] + q[3]) + (q[2] + q[4])) + ((q[5] + q[7]) + (q[6] + q[8])));
-            if (own) {
-                const int64_t at = (int64_t)y * g.pitch + xc;
+        C q[RPI][9];
+        C anchor = (C)0;
 #pragma unroll
-                for (int i = 0; i < 9; ++i) P::st(pd[i] + at, q[i], o.of(i));
+        for (int m = 0; m < RPI; ++m) {
+            const C(&R)[9] = Bf[(J * RPI + m) % NB];
+            if (m > 0 && b + m >= nrows) break;
+            // Ring rows y-2 .. y+2 of lattice row y = walk row b+m.
+            auto slot = [&](int dy) {
+                int v = s0 + m + 2 + dy * dir;
+                return v >= RS ? v - RS : v;
+            };
+            const C* rm2 = ring[slot(-2)];
+            const C* rm1 = ring[slot(-1)];
+            const C* rc = ring[slot(0)];
+            const C* rp1 = ring[slot(1)];
+            const C* rp2 = ring[slot(2)];
+            const int c = tid + 2;
+
+            const C p = rc[c];
+            // psi(x + dx, y + dy), named by direction.
+            const C e1 = rc[c + 1], w1 = rc[c - 1], n1 = rp1[c], s1v = rm1[c];
+            const C ne = rp1[c + 1], nw = rp1[c - 1], sw = rm1[c - 1], se = rm1[c + 1];
+            const C e2 = rc[c + 2], w2 = rc[c - 2], n2 = rp2[c], s2v = rm2[c];
+            const C e2n = rp1[c + 2], e2s = rm1[c + 2], w2n = rp1[c - 2], w2s = rm1[c - 2];
+            const C n2e = rp2[c + 1], n2w = rp2[c - 1], s2e = rm2[c + 1], s2w = rm2[c - 1];
+            const C ne2 = rp2[c + 2], nw2 = rp2[c - 2], sw2 = rm2[c - 2], se2 = rm2[c + 2];
+
+            if (kEnergy && own) {
+                const C S1 = (e1 + w1) + (n1 + s1v);
+                const C S2 = (ne + sw) + (nw + se);
+                const C S4 = (e2 + w2) + (n2 + s2v);
+                const C S5 = ((e2n + w2s) + (e2s + w2n)) + ((n2e + s2w) + (n2w + s2e));
+                const C S8 = (ne2 + sw2) + (nw2 + se2);
+                const C es = (C)0.5 * p * (k.KE0 * p + k.K1 * S1 + k.K2 * S2);
+                const C em = (C)0.5 * p * (k.K4 * S4 + k.K5 * S5 + k.K8 * S8);
+                aM += (double)density(R);
+                aEs += (double)es;
+                aEm += (double)em;
+                aS2 += (double)p * (double)p;
+            }
+
+            if (kCollide) {
+                // eq. (FORCE): F = -psi(x) sum_k K_k psi(x + c_k) c_k, links
+                // paired with their opposites.
+                const C sumx = k.K1 * (e1 - w1) + k.K2 * ((ne + se) - (nw + sw)) +
+                               (C)2 * k.K4 * (e2 - w2) +
+                               k.K5 * ((C)2 * ((e2n + e2s) - (w2n + w2s)) + ((n2e + s2e) - (n2w + s2w))) +
+                               (C)2 * k.K8 * ((ne2 + se2) - (nw2 + sw2));
+                const C sumy = k.K1 * (n1 - s1v) + k.K2 * ((ne + nw) - (se + sw)) +
+                               (C)2 * k.K4 * (n2 - s2v) +
+                               k.K5 * ((C)2 * ((n2e + n2w) - (s2e + s2w)) + ((e2n + w2n) - (e2s + w2s))) +
+                               (C)2 * k.K8 * ((ne2 + nw2) - (se2 + sw2));
+                const C Fx = -p * sumx;
+                const C Fy = -p * sumy;
+
+                // BGK collision at u_eq = (j + tau F) / rho.
+                const C rho = density(R);
+                const C jx = (R[1] - R[3]) + ((R[5] - R[7]) + (R[8] - R[6]));
+                const C jy = (R[2] - R[4]) + ((R[5] - R[7]) + (R[6] - R[8]));
+                const C inv = (C)1 / rho;
+                const C ux = (jx + k.tau * Fx) * inv;
+                const C uy = (jy + k.tau * Fy) * inv;
+                const C usq = (C)1.5 * (ux * ux + uy * uy);
+                const C r1 = rho * ((C)1 / (C)9);
+                const C r2 = rho * ((C)1 / (C)36);
+                const C om = k.omega;
+                auto axis = [&](C cu) { return r1 * ((C)1 + (C)3 * cu + (C)4.5 * cu * cu - usq); };
+                auto diag = [&](C cu) { return r2 * ((C)1 + (C)3 * cu + (C)4.5 * cu * cu - usq); };
+                C* Q = q[m];
+                Q[1] = R[1] + om * (axis(ux) - R[1]);
+                Q[2] = R[2] + om * (axis(uy) - R[2]);
+                Q[3] = R[3] + om * (axis(-ux) - R[3]);
+                Q[4] = R[4] + om * (axis(-uy) - R[4]);
+                Q[5] = R[5] + om * (diag(ux + uy) - R[5]);
+                Q[6] = R[6] + om * (diag(uy - ux) - R[6]);
+                Q[7] = R[7] + om * (diag(-ux - uy) - R[7]);
+                Q[8] = R[8] + om * (diag(ux - uy) - R[8]);
+                // The collision conserves mass exactly; take the rest
+                // population from that so rounding cannot drift the mass.
+                Q[0] = rho - (((Q[1] + Q[3]) + (Q[2] + Q[4])) + ((Q[5] + Q[7]) + (Q[6] + Q[8])));
+                if (m == 0) anchor = Q[0];
+            } else if (m == 0) {
+                anchor = p;
             }
         }
 
+        // Stage psi of the lead rows (their loads have had the barrier and
+        // the arithmetic above to arrive).  Rows past the end of the walk
+        // write slots nobody reads any more.  The empty asm statements tie
+        // the lead-row registers to the result of the arithmetic, so the
+        // compiler cannot hoist this staging (and the wait for those loads)
+        // above the arithmetic; the fence after it keeps the stores below,
+        // so the wait does not also cover this iteration's stores.
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            R0[i] = R1[i];
-            R1[i] = L[i];
+        for (int m = 0; m < RPI; ++m) {
+            C(&NF)[9] = Bf[(J * RPI + RPI + 2 + m) % NB];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(NF[i]) : "v"(anchor));
+            asm volatile("" : "+v"(hvl[m]) : "v"(anchor));
+            int sl = s0 + RPI + 4 + m;
+            sl = sl >= RS ? sl - RS : sl;
+            ring[sl][tid + 2] = psi_of(density(NF), k);
+            halo_psi(hvl[m], sl);
         }
-        s0 = s1;
+        __builtin_amdgcn_sched_barrier(0);
+
+        if (kCollide && own) {
+#pragma unroll
+            for (int m = 0; m < RPI; ++m) {
+                if (m > 0 && b + m >= nrows) break;
+                const int64_t at = (int64_t)wrow(b + m) * g.pitch + xc;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) P::st(pd[i] + at, q[m][i], o.of(i));
+            }
+        }
+    };
+
+    auto step_slot = [](int s) { return s + RPI >= RS ? s + RPI - RS : s + RPI; };
+    int s0 = 0;  // ring slot of walk row b - 2
+#pragma unroll 1
+    for (int it = 0;;) {
+        group(Ic<0>{}, it, s0);
+        s0 = step_slot(s0);
+        if (++it * RPI >= nrows) break;
+        group(Ic<1 % U>{}, it, s0);
+        s0 = step_slot(s0);
+        if (++it * RPI >= nrows) break;
+        group(Ic<2 % U>{}, it, s0);
+        s0 = step_slot(s0);
+        if (++it * RPI >= nrows) break;
+        if constexpr (U == 4) {
+            group(Ic<3>{}, it, s0);
+            s0 = step_slot(s0);
+            if (++it * RPI >= nrows) break;
+        }
     }
 
     if (kEnergy) {
-        __shared__ double red[4][NT / 64];
+        __shared__ double red[4][kWaves];
         double v[4] = {aM, aEs, aEm, aS2};
-        const int lane = tid & 63, wid = tid >> 6;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             v[q] = wave_sum(v[q]);
@@ -336,7 +472,7 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
         __syncthreads();
         if (tid < 4) {
             double s = 0.0;
-            for (int w = 0; w < NT / 64; ++w) s += red[tid][w];
+            for (int w = 0; w < kWaves; ++w) s += red[tid][w];
             partials[(int64_t)lb * 4 + tid] = s;
         }
     }
@@ -451,7 +587,7 @@ k_state(const W* __restrict__ in, W* __restrict__ out, Geom g)
         out[s] = in[d];
 }
 
-template <class P, int NT>
+template <class P, int NT, int RPI>
 hipError_t step_nt(int mode, const void* src, void* dst, const Geom& g,
                    const Coef& c, double* partials, hipStream_t s)
 {
@@ -461,12 +597,20 @@ hipError_t step_nt(int mode, const void* src, void* dst, const Geom& g,
     const S* a = static_cast<const S*>(src);
     S* b = static_cast<S*>(dst);
     if (mode == MODE_STEP)
-        hipLaunchKernelGGL((k_step<P, NT, MODE_STEP>), grid, block, 0, s, a, b, g, k, partials);
+        hipLaunchKernelGGL((k_step<P, NT, MODE_STEP, RPI>), grid, block, 0, s, a, b, g, k, partials);
     else if (mode == MODE_STEP_ENERGY)
-        hipLaunchKernelGGL((k_step<P, NT, MODE_STEP_ENERGY>), grid, block, 0, s, a, b, g, k, partials);
+        hipLaunchKernelGGL((k_step<P, NT, MODE_STEP_ENERGY, RPI>), grid, block, 0, s, a, b, g, k, partials);
     else
-        hipLaunchKernelGGL((k_step<P, NT, MODE_ENERGY>), grid, block, 0, s, a, b, g, k, partials);
+        hipLaunchKernelGGL((k_step<P, NT, MODE_ENERGY, RPI>), grid, block, 0, s, a, b, g, k, partials);
     return hipGetLastError();
+}
+
+template <class P, int NT>
+hipError_t step_rpi(int mode, const void* src, void* dst, const Geom& g,
+                    const Coef& c, double* partials, hipStream_t s)
+{
+    return g.rows_per_iter == 2 ? step_nt<P, NT, 2>(mode, src, dst, g, c, partials, s)
+                                : step_nt<P, NT, 1>(mode, src, dst, g, c, partials, s);
 }
 
 template <class P>
@@ -474,9 +618,9 @@ hipError_t step_p(int mode, const void* src, void* dst, const Geom& g,
                   const Coef& c, double* partials, hipStream_t s)
 {
     switch (g.tile_x) {
-    case 64: return step_nt<P, 64>(mode, src, dst, g, c, partials, s);
-    case 128: return step_nt<P, 128>(mode, src, dst, g, c, partials, s);
-    case 256: return step_nt<P, 256>(mode, src, dst, g, c, partials, s);
+    case 64: return step_rpi<P, 64>(mode, src, dst, g, c, partials, s);
+    case 128: return step_rpi<P, 128>(mode, src, dst, g, c, partials, s);
+    case 256: return step_rpi<P, 256>(mode, src, dst, g, c, partials, s);
     default: return hipErrorInvalidValue;
     }
 }

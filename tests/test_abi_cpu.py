@@ -36,9 +36,9 @@ def test_library_exports_every_declared_symbol():
 
 
 def test_params_struct_layout_matches_header():
-    # int32 x6, int64, double x5 -> 72 bytes, trace_cap at 24, tau at 32.
-    assert ctypes.sizeof(B.lb_params) == 72
-    assert B.lb_params.trace_cap.offset == 24 and B.lb_params.tau.offset == 32
+    # int32 x8, int64, double x5 -> 80 bytes, trace_cap at 32, tau at 40.
+    assert ctypes.sizeof(B.lb_params) == 80
+    assert B.lb_params.trace_cap.offset == 32 and B.lb_params.tau.offset == 40
 
 
 def good(**kw):
@@ -52,7 +52,7 @@ def good(**kw):
 @pytest.mark.parametrize("field,value", [
     ("nx", 4), ("ny", 3), ("storage", 7), ("tau", 0.5), ("tau", float("nan")),
     ("rho0", 0.0), ("G1", float("inf")), ("log_every", -1), ("trace_cap", -2),
-    ("tile_x", 96), ("tile_y", -1), ("tile_y", 5000)])
+    ("tile_x", 96), ("tile_y", -1), ("tile_y", 5000), ("tile_rows", 3), ("reserved", 1)])
 def test_validation_rejects(field, value):
     p = good()
     setattr(p, field, value)
@@ -70,8 +70,8 @@ def test_f16_needs_positive_reference():
 
 def test_workspace_and_launch_shape():
     p = good(nx=2048, ny=2048, trace_cap=41)
-    tx, ty, nb = P.lb_launch_shape(p)
-    assert tx == 256 and ty >= 1 and nb == (2048 // tx) * math.ceil(2048 / ty)
+    tx, ty, tr, nb = P.lb_launch_shape(p)
+    assert tx == 256 and ty >= 1 and tr in (1, 2) and nb == (2048 // tx) * math.ceil(2048 / ty)
     # Two population buffers of 9 planes plus bookkeeping.
     assert P.lb_workspace_bytes(p) >= 2 * 9 * 2048 * 2048 * 4
     small = good(nx=5, ny=5)

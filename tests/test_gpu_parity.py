@@ -70,20 +70,26 @@ def test_f64_workload_fields_and_trace():
     sim.close()
 
 
-@pytest.mark.parametrize("nx,ny,tile_x,tile_y", [
-    (100, 70, 64, 16),     # ragged in x and y
-    (130, 37, 128, 5),
-    (300, 90, 256, 64),
-    (5, 5, 64, 1),          # smallest lattice: every link wraps
-    (7, 5, 64, 3),
-    (5, 9, 64, 16),
-    (257, 11, 256, 4)])
-def test_f64_populations_match_oracle(nx, ny, tile_x, tile_y):
+@pytest.mark.parametrize("nx,ny,tile_x,tile_y,tile_rows", [
+    (100, 70, 64, 16, 1),     # ragged in x and y
+    (130, 37, 128, 5, 1),
+    (300, 90, 256, 64, 1),
+    (5, 5, 64, 1, 1),          # smallest lattice: every link wraps
+    (7, 5, 64, 3, 1),
+    (5, 9, 64, 16, 1),
+    (257, 11, 256, 4, 1),
+    (100, 70, 64, 16, 2),     # two rows per pipeline stage
+    (130, 37, 128, 5, 2),     # odd rows per tile
+    (5, 5, 64, 1, 2),
+    (7, 6, 64, 3, 2),
+    (300, 91, 256, 33, 2)])
+def test_f64_populations_match_oracle(nx, ny, tile_x, tile_y, tile_rows):
     G1, G2 = R01
     rho0 = inputs.rho_noise(nx, ny, 3)
     steps = 150
     fo = oracle_f(rho0, steps, G1, G2, tau=0.8)
-    sim = gpu_run(rho0, steps, G1, G2, tau=0.8, tile_x=tile_x, tile_y=tile_y)
+    sim = gpu_run(rho0, steps, G1, G2, tau=0.8, tile_x=tile_x, tile_y=tile_y,
+                  tile_rows=tile_rows)
     fg = sim.get_state()
     assert dmax(fg, fo) <= 1e-10
     sim.close()
@@ -93,8 +99,9 @@ def test_fields_bit_identical_across_launch_shapes():
     G1, G2 = R01
     rho0 = inputs.rho_noise(300, 90, 4)
     states = []
-    for tx, ty in [(64, 1), (64, 16), (128, 7), (256, 64), (256, 90)]:
-        sim = gpu_run(rho0, 60, G1, G2, storage="f32", tile_x=tx, tile_y=ty)
+    for tx, ty, tr in [(64, 1, 1), (64, 16, 1), (128, 7, 1), (256, 64, 1), (256, 90, 1),
+                       (64, 1, 2), (128, 7, 2), (256, 32, 2), (256, 90, 2)]:
+        sim = gpu_run(rho0, 60, G1, G2, storage="f32", tile_x=tx, tile_y=ty, tile_rows=tr)
         states.append(sim.get_state())
         sim.close()
     for s in states[1:]:

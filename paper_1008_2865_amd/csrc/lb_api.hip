@@ -88,8 +88,10 @@ int check_params(const lb_params* p)
     if (!p) return fail(LB_ERR_INVALID, "params is NULL");
     if (p->nx < 5 || p->ny < 5)
         return fail(LB_ERR_INVALID, "nx, ny must be >= 5 (got %d x %d)", p->nx, p->ny);
-    if ((int64_t)p->nx * p->ny >= (int64_t(1) << 31))
-        return fail(LB_ERR_INVALID, "nx*ny must be < 2^31");
+    // One population plane, padded rows included, must be indexable with
+    // 32-bit offsets.
+    if (((int64_t)p->nx + 192) * p->ny >= (int64_t(1) << 31))
+        return fail(LB_ERR_INVALID, "(nx + 192) * ny must be < 2^31");
     if (p->storage != LB_F64 && p->storage != LB_F32 && p->storage != LB_F16DEV)
         return fail(LB_ERR_INVALID, "unknown storage %d", p->storage);
     if (p->log_every < 0) return fail(LB_ERR_INVALID, "log_every must be >= 0");
@@ -124,7 +126,7 @@ Geom make_geom(const lb_params& p)
     // workgroups touch) do not sit at power-of-two strides, which would
     // pile their accesses onto the same HBM channels.
     g.pitch = (p.nx + 63) / 64 * 64;
-    if ((g.pitch / 64) % 2 == 0) g.pitch += 64;
+    if ((g.pitch / 64) % 2 == 0) g.pitch += 64;  // pitch <= nx + 127
     g.plane = (int64_t)p.ny * g.pitch;
     g.tile_x = p.tile_x ? p.tile_x : (p.nx >= 256 ? 256 : p.nx >= 128 ? 128 : 64);
     g.tile_y = p.tile_y ? p.tile_y : 32;

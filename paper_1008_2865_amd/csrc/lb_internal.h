@@ -23,7 +23,7 @@ enum Mode {
 // (x fastest, pitch a multiple of 64 elements), planes `plane` elements apart.
 struct Geom {
     int32_t nx, ny;
-    int64_t pitch;    // elements per row
+    int32_t pitch;    // elements per row; ny * pitch < 2^31
     int64_t plane;    // elements per population plane
     int32_t tile_x;   // columns per workgroup (= threads per workgroup)
     int32_t tile_y;   // rows per workgroup

@@ -71,8 +71,14 @@ CoefT<C> convert(const Coef& c)
                     (C)c.rho_ref};
 }
 
+// Single-precision arithmetic uses the hardware exponential and reciprocal
+// (about 1 ulp each; the single-precision path is held to the error the
+// rounding of single precision itself produces, far above that).  Double
+// precision uses the correctly rounded library functions.
 __device__ __forceinline__ double exp_c(double v) { return exp(v); }
-__device__ __forceinline__ float exp_c(float v) { return expf(v); }
+__device__ __forceinline__ float exp_c(float v) { return __expf(v); }
+__device__ __forceinline__ double rcp_c(double v) { return 1.0 / v; }
+__device__ __forceinline__ float rcp_c(float v) { return __builtin_amdgcn_rcpf(v); }
 
 template <typename C>
 __device__ __forceinline__ C psi_of(C rho, const CoefT<C>& k)
@@ -127,8 +133,8 @@ __device__ __forceinline__ void pull(const typename P::S* const* pl,
 {
     const int ym = y == 0 ? g.ny - 1 : y - 1;
     const int yp = y == g.ny - 1 ? 0 : y + 1;
-    const int64_t r0 = (int64_t)y * g.pitch, rm = (int64_t)ym * g.pitch,
-                  rp = (int64_t)yp * g.pitch;
+    // Offsets inside one plane fit in 32 bits (the host checks it).
+    const int r0 = y * g.pitch, rm = ym * g.pitch, rp = yp * g.pitch;
     f[0] = P::ld(pl[0] + r0 + x, o.o0);
     f[1] = P::ld(pl[1] + r0 + xm, o.o1);  // c = ( 1, 0)
     f[2] = P::ld(pl[2] + rm + x, o.o1);   // c = ( 0, 1)
@@ -261,8 +267,7 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
         // every lane of the wave shares.
         const int ym = y == 0 ? ny - 1 : y - 1;
         const int yp = y == ny - 1 ? 0 : y + 1;
-        const int64_t r = hcy > 0 ? (int64_t)ym * g.pitch
-                                  : (hcy < 0 ? (int64_t)yp * g.pitch : (int64_t)y * g.pitch);
+        const int r = (hcy > 0 ? ym : (hcy < 0 ? yp : y)) * g.pitch;
         return P::ld(hp + r, hoff);
     };
     auto halo_psi = [&](C hv, int slot) {
@@ -383,7 +388,7 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
                 const C rho = density(R);
                 const C jx = (R[1] - R[3]) + ((R[5] - R[7]) + (R[8] - R[6]));
                 const C jy = (R[2] - R[4]) + ((R[5] - R[7]) + (R[6] - R[8]));
-                const C inv = (C)1 / rho;
+                const C inv = rcp_c(rho);
                 const C ux = (jx + k.tau * Fx) * inv;
                 const C uy = (jy + k.tau * Fy) * inv;
                 const C usq = (C)1.5 * (ux * ux + uy * uy);
@@ -434,7 +439,7 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
 #pragma unroll
             for (int m = 0; m < RPI; ++m) {
                 if (m > 0 && b + m >= nrows) break;
-                const int64_t at = (int64_t)wrow(b + m) * g.pitch + xc;
+                const int at = wrow(b + m) * g.pitch + xc;
 #pragma unroll
                 for (int i = 0; i < 9; ++i) P::st(pd[i] + at, q[m][i], o.of(i));
             }

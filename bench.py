@@ -65,10 +65,11 @@ def cpu_baseline(n, G1, G2, seed, target_s, steps=None):
 
     f = O.init(inputs.rho_noise(n, n, seed))
     if steps is None:
+        f = O.step(f, 1, 1.0, 1.0, G1, G2)  # warm the threads and pages
         t0 = time.perf_counter()
-        f = O.step(f, 1, 1.0, 1.0, G1, G2)
-        one = time.perf_counter() - t0
-        steps = int(max(1, min(500, target_s / max(one, 1e-6))))
+        f = O.step(f, 2, 1.0, 1.0, G1, G2)
+        one = (time.perf_counter() - t0) / 2
+        steps = int(max(1, min(5000, target_s / max(one, 1e-6))))
     t0 = time.perf_counter()
     O.step(f, steps, 1.0, 1.0, G1, G2)
     dt = time.perf_counter() - t0

@@ -80,6 +80,7 @@ Coef make_coef(const lb_params& p)
     c.sqrt_rho0 = std::sqrt(p.rho0);
     c.inv_rho0 = 1.0 / p.rho0;
     c.rho_ref = p.storage == LB_F16DEV ? p.rho_ref : 0.0;
+    c.step = 0;
     return c;
 }
 
@@ -217,6 +218,7 @@ int field_check_host(const double* v, int64_t n, bool positive, const char* name
 
 int energy_row(lb_ctx* c, int mode, const void* src, void* dst, double* row)
 {
+    c->coef.step = (uint32_t)c->t;
     hipError_t e = lbk::launch_step(c->p.storage, mode, src, dst, c->g, c->coef, c->partials, c->stream);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     e = lbk::launch_final(c->partials, c->g.blocks, (double)c->t, 0.5 * (c->p.G1 + c->p.G2), row,
@@ -404,6 +406,7 @@ int lb_step(lb_ctx* c, int64_t n)
             c->last_logged = c->t;
             ++c->trace_rows;
         } else {
+            c->coef.step = (uint32_t)c->t;
             hipError_t e = lbk::launch_step(c->p.storage, lbk::MODE_STEP, src, dst, c->g, c->coef,
                                             c->partials, c->stream);
             if (e) return hip_fail(e, "step kernel launch");

@@ -40,6 +40,7 @@ struct Coef {
     double tau, omega;          // BGK relaxation time and 1/tau
     double sqrt_rho0, inv_rho0; // psi = sqrt(rho0) (1 - exp(-rho/rho0))
     double rho_ref;             // deviation reference of ST_F16DEV
+    uint32_t step;              // time step of the launch
 };
 
 // Bytes of one stored population value.

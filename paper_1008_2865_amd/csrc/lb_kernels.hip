@@ -58,9 +58,36 @@ struct PF16 {
     __device__ static void st(S* p, C v, C off) { *p = (S)(v - off); }
 };
 
+// Counter-based hash of (site, step): 32 well-mixed bits (the murmur3
+// finaliser applied to a combination of the coordinates).
+__device__ __forceinline__ uint32_t site_hash(uint32_t x, uint32_t y, uint32_t t)
+{
+    uint32_t h = x * 0x9E3779B1u ^ (y + 0x7F4A7C15u) * 0x85EBCA77u ^ (t + 0x165667B1u) * 0xC2B2AE3Du;
+    h ^= h >> 16;
+    h *= 0x85EBCA6Bu;
+    h ^= h >> 13;
+    h *= 0xC2B2AE35u;
+    h ^= h >> 16;
+    return h;
+}
+
+// float -> half with stochastic rounding: the 13 mantissa bits half drops
+// are replaced by a carry from r, so the result rounds up with probability
+// equal to the dropped fraction (unbiased).  Outside the half normal range
+// it falls back to round-to-nearest.
+__device__ __forceinline__ _Float16 half_stochastic(float v, uint32_t r)
+{
+    const uint32_t b = __float_as_uint(v);
+    uint32_t mag = b & 0x7fffffffu;
+    if (mag < 0x38800000u || mag >= 0x477fe000u) return (_Float16)v;
+    mag = (mag + (r & 0x1fffu)) & ~0x1fffu;
+    return (_Float16)__uint_as_float((b & 0x80000000u) | mag);
+}
+
 template <typename C>
 struct CoefT {
     C K1, K2, K4, K5, K8, KE0, tau, omega, sqrt_rho0, inv_rho0, rho_ref;
+    uint32_t step;  // time step of the launch (seeds the stochastic rounding)
 };
 
 template <typename C>
@@ -68,7 +95,7 @@ CoefT<C> convert(const Coef& c)
 {
     return CoefT<C>{(C)c.K1, (C)c.K2, (C)c.K4, (C)c.K5, (C)c.K8, (C)c.KE0,
                     (C)c.tau, (C)c.omega, (C)c.sqrt_rho0, (C)c.inv_rho0,
-                    (C)c.rho_ref};
+                    (C)c.rho_ref, c.step};
 }
 
 // Single-precision arithmetic uses the hardware exponential and reciprocal
@@ -122,6 +149,33 @@ struct Offs {
     }
     __device__ typename P::C of(int i) const { return i == 0 ? o0 : (i < 5 ? o1 : o2); }
 };
+
+// Store the nine post-collision populations of one site.  For the half
+// storage the moving populations are rounded to nearest, and the rest
+// population absorbs their rounding errors (so the stored populations of a
+// site sum to its density up to a single rounding) and is itself rounded
+// stochastically: at a uniform state every site would otherwise make the
+// same rounding error at every step and the total mass would drift.
+template <class P>
+__device__ __forceinline__ void store_site(typename P::S* const* pd, int at,
+                                           const typename P::C q[9],
+                                           const Offs<P>& o, uint32_t rnd)
+{
+    if constexpr (P::kDev) {
+        float resid = q[0] - o.o0;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) {
+            const float d = q[i] - o.of(i);
+            const _Float16 h = (_Float16)d;
+            resid += d - (float)h;
+            pd[i][at] = h;
+        }
+        pd[0][at] = half_stochastic(resid, rnd);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) P::st(pd[i] + at, q[i], o.of(i));
+    }
+}
 
 // Pull the nine populations arriving at (x, y): f_i(x, t) = stored_i(x - c_i).
 // xm/xp are the periodic columns x-1 / x+1.
@@ -439,9 +493,9 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
 #pragma unroll
             for (int m = 0; m < RPI; ++m) {
                 if (m > 0 && b + m >= nrows) break;
-                const int at = wrow(b + m) * g.pitch + xc;
-#pragma unroll
-                for (int i = 0; i < 9; ++i) P::st(pd[i] + at, q[m][i], o.of(i));
+                const int yw = wrow(b + m);
+                const uint32_t rnd = P::kDev ? site_hash(xc, yw, k.step) : 0u;
+                store_site<P>(pd, yw * g.pitch + xc, q[m], o, rnd);
             }
         }
     };

@@ -171,6 +171,49 @@ int lb_destroy(lb_ctx* c);
 /* Message describing the last failure on the calling thread. */
 const char* lb_last_error(void);
 
+/* ---------------------------------------------------------------------------
+ * Batches: many independent periodic lattices, each with its own size,
+ * couplings and initial density, advanced together by one kernel launch
+ * per time step (the step of every lattice is exactly the one lb_step
+ * performs, so its fields are bit-identical to a lb_step run of the same
+ * lattice and launch shape).
+ * ------------------------------------------------------------------------ */
+typedef struct lb_batch lb_batch;
+
+/* Workspace bytes for `count` lattices with parameters ps[0..count-1], or 0
+ * if they are invalid.  All lattices must share storage, tile_x, tile_rows,
+ * log_every and trace_cap (after the library's defaults are applied);
+ * sizes, tile_y, tau, rho0, G1, G2 and rho_ref may differ. */
+size_t lb_batch_workspace_bytes(const lb_params* ps, int32_t count);
+
+/* Create a batch at t = 0; lattice i starts at rest with density
+ * rho_init[i] (ny_i * nx_i doubles, host or device memory per
+ * inputs_on_device).  Workspace and stream rules are those of lb_init.
+ * When the stream is not the null stream, runs of plain steps are captured
+ * into HIP graphs (one per run length and buffer parity) and replayed. */
+int lb_batch_init(lb_batch** out, const lb_params* ps, int32_t count,
+                  void* workspace, size_t bytes, const double* const* rho_init,
+                  int inputs_on_device, void* hip_stream);
+
+/* Advance every lattice n >= 0 steps, asynchronously.  With log_every > 0
+ * the energies of each lattice are recorded at every log point in
+ * [t, t+n], the state reached at t+n included, in each lattice's trace
+ * (read with lb_trace on its member context).  LB_ERR_STATE, with nothing
+ * launched, if the traces cannot hold the new rows. */
+int lb_batch_step(lb_batch* b, int64_t n);
+
+/* Turn graph capture of plain steps on or off (LB_ERR_INVALID to turn it
+ * on for the null stream). */
+int lb_batch_use_graphs(lb_batch* b, int enable);
+
+/* Context of lattice i, owned by the batch: lb_moments, lb_pseudo_energy,
+ * lb_trace, lb_time and lb_get_state accept it; lb_step, lb_set_state and
+ * lb_destroy reject it with LB_ERR_STATE. */
+int lb_batch_member(lb_batch* b, int32_t i, lb_ctx** member);
+
+/* Release the batch and its member contexts (after synchronising). */
+int lb_batch_destroy(lb_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,107 @@
+"""Launch-shape autotuner for the step kernel.
+
+Times candidate launch shapes (columns per workgroup, rows per workgroup,
+rows per pipeline stage) on the GPU for a lattice size and storage, and
+caches the fastest in a JSON file (``LB_TUNE_CACHE``, default
+``~/.cache/paper_1008_2865_amd/tiles.json``).  Every candidate runs the
+same library kernels; the tuner only chooses among launch shapes, which do
+not change the computed fields.
+"""
+import json
+import os
+
+DEFAULT_CANDIDATES = [(256, 32, 1), (256, 16, 1), (128, 32, 1), (256, 32, 2), (128, 16, 1),
+                      (64, 32, 1), (256, 64, 2)]
+
+
+def cache_path():
+    return os.environ.get("LB_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_1008_2865_amd",
+                                       "tiles.json"))
+
+
+def _load():
+    try:
+        with open(cache_path()) as fh:
+            return json.load(fh)
+    except (OSError, ValueError):
+        return {}
+
+
+def _save(d):
+    path = cache_path()
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as fh:
+        json.dump(d, fh, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def time_shape(nx, ny, storage, tile_x, tile_y, tile_rows, steps=100, warmup=20):
+    """Microseconds per step of the step kernel for one launch shape."""
+    import torch
+
+    from . import inputs
+    from .sim import LBSim
+
+    G1, G2 = inputs.couplings(0.1)
+    sim = LBSim(inputs.rho_noise(nx, ny, 1), G1=G1, G2=G2, storage=storage, tile_x=tile_x,
+                tile_y=tile_y, tile_rows=tile_rows)
+    sim.step(warmup)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    sim.step(steps)
+    b.record()
+    torch.cuda.synchronize()
+    sim.close()
+    return a.elapsed_time(b) * 1e3 / steps
+
+
+def tune(nx, ny, storage="f32", candidates=None, refresh=False, steps=100):
+    """Fastest (tile_x, tile_y, tile_rows) for this size and storage."""
+    key = f"{storage}:{nx}x{ny}"
+    cache = _load()
+    if not refresh and key in cache:
+        c = cache[key]
+        return c["tile_x"], c["tile_y"], c["tile_rows"]
+    cands = candidates or DEFAULT_CANDIDATES
+    if storage == "f64":
+        cands = [c for c in cands if c[2] == 1]
+    best = None
+    for tx, ty, tr in cands:
+        if tx > max(64, nx):
+            continue
+        us = time_shape(nx, ny, storage, tx, min(ty, ny), tr, steps=steps)
+        if best is None or us < best[0]:
+            best = (us, tx, min(ty, ny), tr)
+    cache[key] = {"tile_x": best[1], "tile_y": best[2], "tile_rows": best[3], "us_per_step": best[0]}
+    _save(cache)
+    return best[1], best[2], best[3]
+
+
+def tune_batch(shapes, storage="f32", tile_x=None, tile_rows=1, tile_ys=(8, 16, 32, 64),
+               refresh=False, steps=100):
+    """Shared (tile_x, tile_rows) and a tile_y per distinct (ny, nx) for a
+    batch: tile_x is the widest strip every lattice fills unless given;
+    tile_y is tuned per size with that strip width."""
+    if tile_x is None:
+        m = min(nx for _, nx in shapes)
+        tile_x = 256 if m >= 256 else 128 if m >= 128 else 64
+    cache = _load()
+    per = {}
+    for ny, nx in sorted(set(map(tuple, shapes))):
+        key = f"{storage}:{nx}x{ny}:x{tile_x}:r{tile_rows}"
+        if not refresh and key in cache:
+            per[(ny, nx)] = cache[key]["tile_y"]
+            continue
+        best = None
+        for ty in tile_ys:
+            ty = min(ty, ny)
+            us = time_shape(nx, ny, storage, tile_x, ty, tile_rows, steps=steps)
+            if best is None or us < best[0]:
+                best = (us, ty)
+        cache[key] = {"tile_y": best[1], "us_per_step": best[0]}
+        per[(ny, nx)] = best[1]
+    _save(cache)
+    return tile_x, tile_rows, per

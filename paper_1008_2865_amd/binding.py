@@ -60,6 +60,13 @@ SIGNATURES = {
     "lb_tables": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp]),
     "lb_destroy": (ctypes.c_int, [_vp]),
     "lb_last_error": (ctypes.c_char_p, []),
+    "lb_batch_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int32]),
+    "lb_batch_init": (ctypes.c_int, [ctypes.POINTER(_vp), _P, ctypes.c_int32, _vp, ctypes.c_size_t,
+                                     ctypes.POINTER(_vp), ctypes.c_int, _vp]),
+    "lb_batch_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
+    "lb_batch_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lb_batch_member": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]),
+    "lb_batch_destroy": (ctypes.c_int, [_vp]),
 }
 
 _lib = None
@@ -172,3 +179,41 @@ def lb_destroy(ctx):
 
 def lb_last_error():
     return lib().lb_last_error().decode(errors="replace")
+
+
+def _params_array(ps):
+    arr = (lb_params * len(ps))()
+    for i, p in enumerate(ps):
+        arr[i] = p
+    return arr
+
+
+def lb_batch_workspace_bytes(ps):
+    return lib().lb_batch_workspace_bytes(_params_array(ps), len(ps))
+
+
+def lb_batch_init(ps, workspace, nbytes, rho_inits, inputs_on_device=False, stream=0):
+    arr = _params_array(ps)
+    ptrs = (_vp * len(ps))(*[_ptr(r) for r in rho_inits])
+    b = _vp()
+    _check(lib().lb_batch_init(ctypes.byref(b), arr, len(ps), _ptr(workspace), nbytes, ptrs,
+                               int(bool(inputs_on_device)), stream or None))
+    return b.value
+
+
+def lb_batch_step(b, n):
+    return _check(lib().lb_batch_step(b, n))
+
+
+def lb_batch_use_graphs(b, enable):
+    return _check(lib().lb_batch_use_graphs(b, int(bool(enable))))
+
+
+def lb_batch_member(b, i):
+    m = _vp()
+    _check(lib().lb_batch_member(b, i, ctypes.byref(m)))
+    return m.value
+
+
+def lb_batch_destroy(b):
+    return _check(lib().lb_batch_destroy(b))

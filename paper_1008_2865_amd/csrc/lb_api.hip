@@ -13,8 +13,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <set>
+#include <utility>
 #include <string>
 #include <vector>
 
@@ -176,6 +178,22 @@ struct lb_ctx {
     int64_t t;
     int64_t trace_rows;
     int64_t last_logged;
+    lb_batch* batch;  // non-NULL for a lattice owned by a batch
+};
+
+struct lb_batch {
+    std::vector<lb_ctx*> members;
+    lbk::BatchLattice* desc;   // device
+    int32_t* tile_lattice;     // device
+    double* partials;          // device, 4 per tile
+    int tiles;
+    int storage, tile_x, rows_per_iter;
+    int device;
+    hipStream_t stream;
+    int parity;
+    int64_t t, log_every, trace_cap, trace_rows, last_logged;
+    bool use_graphs;
+    std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
 };
 
 namespace {
@@ -344,6 +362,7 @@ int lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t bytes,
     c->t = 0;
     c->trace_rows = 0;
     c->last_logged = -1;
+    c->batch = nullptr;
 
     const double *r = rho_init, *u = ux_init, *v = uy_init;
     if (!inputs_on_device) {
@@ -378,6 +397,7 @@ int lb_step(lb_ctx* c, int64_t n)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
+    if (c->batch) return fail(LB_ERR_STATE, "this lattice belongs to a batch: step it with lb_batch_step");
     if (n < 0) return fail(LB_ERR_INVALID, "n must be >= 0");
     if (n == 0) return LB_OK;
     const int64_t le = c->p.log_every;
@@ -478,7 +498,8 @@ int lb_trace(lb_ctx* c, double* out, int64_t cap, int64_t* n_rows)
     // Record the current state first if it is a log point not yet recorded
     // and the trace has room.
     const int64_t le = c->p.log_every;
-    if (le > 0 && c->t % le == 0 && c->last_logged != c->t && c->trace_rows < c->p.trace_cap) {
+    if (!c->batch && le > 0 && c->t % le == 0 && c->last_logged != c->t &&
+        c->trace_rows < c->p.trace_cap) {
         if ((rc = energy_row(c, lbk::MODE_ENERGY, c->buf[c->cur], c->buf[c->cur ^ 1],
                              c->trace + c->trace_rows * 6)))
             return rc;
@@ -519,6 +540,7 @@ int lb_set_state(lb_ctx* c, const void* src, int on_device, int64_t t)
 {
     int rc = check_ctx(c);
     if (rc) return rc;
+    if (c->batch) return fail(LB_ERR_STATE, "this lattice belongs to a batch");
     if (!src) return fail(LB_ERR_INVALID, "src is NULL");
     if (t < 0) return fail(LB_ERR_INVALID, "t must be >= 0");
     DeviceGuard dg(c->device);
@@ -547,11 +569,324 @@ int lb_destroy(lb_ctx* c)
     {
         std::lock_guard<std::mutex> lk(g_mu);
         if (!c || !g_live.count(c)) return fail(LB_ERR_STATE, "unknown or destroyed context");
+        if (c->batch) return fail(LB_ERR_STATE, "this lattice belongs to a batch: use lb_batch_destroy");
         g_live.erase(c);
     }
     DeviceGuard dg(c->device);
     hipError_t e = hipStreamSynchronize(c->stream);
     delete c;
+    if (e) return hip_fail(e, "synchronise");
+    return LB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batches of independent lattices.
+// ---------------------------------------------------------------------------
+namespace {
+
+std::set<lb_batch*> g_batches;
+
+int check_batch(lb_batch* b)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!b || !g_batches.count(b)) return fail(LB_ERR_STATE, "unknown or destroyed batch");
+    return LB_OK;
+}
+
+// Workspace of a batch: descriptor table, tile -> lattice table, partials,
+// then one single-lattice workspace per member.
+struct BatchLayout {
+    size_t desc, tile_lattice, partials;
+    std::vector<size_t> member, member_bytes;
+    size_t total;
+    int tiles;
+};
+
+int batch_layout(const lb_params* ps, int32_t count, BatchLayout* L)
+{
+    if (!ps) return fail(LB_ERR_INVALID, "params is NULL");
+    if (count < 1 || count > 65536) return fail(LB_ERR_INVALID, "count must be in [1, 65536]");
+    int rc;
+    L->tiles = 0;
+    Geom g0{};
+    for (int32_t i = 0; i < count; ++i) {
+        if ((rc = check_params(&ps[i]))) {
+            return fail(rc, "lattice %d: %s", i, g_err.c_str());
+        }
+        const Geom g = make_geom(ps[i]);
+        if (i == 0) g0 = g;
+        if (ps[i].storage != ps[0].storage || g.tile_x != g0.tile_x ||
+            g.rows_per_iter != g0.rows_per_iter || ps[i].log_every != ps[0].log_every ||
+            ps[i].trace_cap != ps[0].trace_cap)
+            return fail(LB_ERR_INVALID,
+                        "lattice %d: storage, tile_x, tile_rows, log_every and trace_cap must "
+                        "match lattice 0", i);
+        if ((int64_t)L->tiles + g.blocks >= (int64_t(1) << 30))
+            return fail(LB_ERR_INVALID, "too many tiles in the batch");
+        L->tiles += g.blocks;
+    }
+    size_t off = 0;
+    L->desc = off;
+    off += align_up(sizeof(lbk::BatchLattice) * count);
+    L->tile_lattice = off;
+    off += align_up(sizeof(int32_t) * L->tiles);
+    L->partials = off;
+    off += align_up(sizeof(double) * 4 * L->tiles);
+    L->member.resize(count);
+    L->member_bytes.resize(count);
+    for (int32_t i = 0; i < count; ++i) {
+        L->member[i] = off;
+        L->member_bytes[i] = make_layout(ps[i], make_geom(ps[i])).total;
+        off += L->member_bytes[i];
+    }
+    L->total = off;
+    return LB_OK;
+}
+
+hipError_t batch_launch(lb_batch* b, int mode, int parity)
+{
+    return lbk::launch_step_batch(b->storage, mode, b->tile_x, b->rows_per_iter, b->desc,
+                                  b->tile_lattice, b->tiles, parity, (uint32_t)b->t, b->partials,
+                                  b->stream);
+}
+
+// n plain steps starting from the current parity, as one replay of a
+// captured graph when the stream allows capture, else launch by launch.
+hipError_t batch_plain(lb_batch* b, int64_t n)
+{
+    if (b->use_graphs && n >= 2) {
+        const auto key = std::make_pair(n, b->parity);
+        auto it = b->graphs.find(key);
+        if (it == b->graphs.end()) {
+            hipGraph_t graph = nullptr;
+            hipGraphExec_t exec = nullptr;
+            hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t le = hipSuccess;
+                for (int64_t j = 0; j < n && le == hipSuccess; ++j)
+                    le = batch_launch(b, lbk::MODE_STEP, b->parity ^ (int)(j & 1));
+                e = hipStreamEndCapture(b->stream, &graph);
+                if (e == hipSuccess && le != hipSuccess) e = le;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                // This stream cannot be captured: run launch by launch from now on.
+                (void)hipGetLastError();
+                b->use_graphs = false;
+                return batch_plain(b, n);
+            }
+            it = b->graphs.emplace(key, exec).first;
+        }
+        return hipGraphLaunch(it->second, b->stream);
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        hipError_t e = batch_launch(b, lbk::MODE_STEP, b->parity ^ (int)(j & 1));
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+int batch_log(lb_batch* b, int mode)
+{
+    hipError_t e = batch_launch(b, mode, b->parity);
+    if (!e)
+        e = lbk::launch_final_batch(b->desc, (int)b->members.size(), b->partials, (double)b->t,
+                                    b->trace_rows, b->stream);
+    if (e) return hip_fail(e, "batched energy launch");
+    b->last_logged = b->t;
+    ++b->trace_rows;
+    return LB_OK;
+}
+
+void batch_sync_members(lb_batch* b)
+{
+    for (lb_ctx* c : b->members) {
+        c->t = b->t;
+        c->cur = b->parity;
+        c->trace_rows = b->trace_rows;
+        c->last_logged = b->last_logged;
+    }
+}
+
+}  // namespace
+
+size_t lb_batch_workspace_bytes(const lb_params* ps, int32_t count)
+{
+    BatchLayout L;
+    if (batch_layout(ps, count, &L) != LB_OK) return 0;
+    return L.total;
+}
+
+int lb_batch_init(lb_batch** out, const lb_params* ps, int32_t count, void* workspace,
+                  size_t bytes, const double* const* rho_init, int inputs_on_device,
+                  void* hip_stream)
+{
+    if (!out) return fail(LB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    BatchLayout L;
+    int rc = batch_layout(ps, count, &L);
+    if (rc) return rc;
+    if (!workspace) return fail(LB_ERR_INVALID, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(LB_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
+    if (bytes < L.total) return fail(LB_ERR_INVALID, "workspace too small: %zu < %zu bytes", bytes, L.total);
+    if (!rho_init) return fail(LB_ERR_INVALID, "rho_init is NULL");
+    for (int32_t i = 0; i < count; ++i)
+        if (!rho_init[i]) return fail(LB_ERR_INVALID, "rho_init[%d] is NULL", i);
+
+    char* ws = static_cast<char*>(workspace);
+    lb_batch* b = new lb_batch();
+    b->stream = static_cast<hipStream_t>(hip_stream);
+    std::vector<lbk::BatchLattice> desc(count);
+    std::vector<int32_t> tl(L.tiles);
+    int tile = 0;
+    for (int32_t i = 0; i < count; ++i) {
+        lb_ctx* c = nullptr;
+        rc = lb_init(&c, &ps[i], ws + L.member[i], L.member_bytes[i], rho_init[i], nullptr, nullptr,
+                     inputs_on_device, hip_stream);
+        if (rc) {
+            std::string msg = g_err;
+            for (lb_ctx* m : b->members) {
+                m->batch = nullptr;
+                lb_destroy(m);
+            }
+            delete b;
+            return fail(rc, "lattice %d: %s", i, msg.c_str());
+        }
+        c->batch = b;
+        b->members.push_back(c);
+        lbk::BatchLattice& d = desc[i];
+        std::memset(&d, 0, sizeof d);
+        d.geom = c->g;
+        d.coef = c->coef;
+        d.buf[0] = c->buf[0];
+        d.buf[1] = c->buf[1];
+        d.trace = c->trace;
+        d.half_A1 = 0.5 * (ps[i].G1 + ps[i].G2);
+        d.tile_begin = tile;
+        for (int j = 0; j < c->g.blocks; ++j) tl[tile + j] = i;
+        tile += c->g.blocks;
+    }
+    lb_ctx* c0 = b->members[0];
+    b->desc = reinterpret_cast<lbk::BatchLattice*>(ws + L.desc);
+    b->tile_lattice = reinterpret_cast<int32_t*>(ws + L.tile_lattice);
+    b->partials = reinterpret_cast<double*>(ws + L.partials);
+    b->tiles = L.tiles;
+    b->storage = ps[0].storage;
+    b->tile_x = c0->g.tile_x;
+    b->rows_per_iter = c0->g.rows_per_iter;
+    b->device = c0->device;
+    b->parity = 0;
+    b->t = 0;
+    b->log_every = ps[0].log_every;
+    b->trace_cap = ps[0].trace_cap;
+    b->trace_rows = 0;
+    b->last_logged = -1;
+    b->use_graphs = b->stream != nullptr;
+    hipError_t e = hipMemcpyAsync(b->desc, desc.data(), sizeof(lbk::BatchLattice) * count,
+                                  hipMemcpyHostToDevice, b->stream);
+    if (!e) e = hipMemcpyAsync(b->tile_lattice, tl.data(), sizeof(int32_t) * L.tiles,
+                               hipMemcpyHostToDevice, b->stream);
+    if (!e) e = hipStreamSynchronize(b->stream);
+    if (e) {
+        for (lb_ctx* m : b->members) {
+            m->batch = nullptr;
+            lb_destroy(m);
+        }
+        delete b;
+        return hip_fail(e, "copy batch tables");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_batches.insert(b);
+    }
+    *out = b;
+    return LB_OK;
+}
+
+int lb_batch_step(lb_batch* b, int64_t n)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (n < 0) return fail(LB_ERR_INVALID, "n must be >= 0");
+    const int64_t le = b->log_every;
+    // Rows this call appends: log points in [t, t+n] not recorded yet (the
+    // state reached at t+n is recorded too).
+    int64_t need = 0;
+    if (le > 0) {
+        const int64_t first = (b->t + le - 1) / le * le;
+        if (first <= b->t + n) need = (b->t + n - first) / le + 1;
+        if (b->last_logged == b->t && b->t % le == 0) --need;
+    }
+    if (b->trace_rows + need > b->trace_cap)
+        return fail(LB_ERR_STATE, "trace full: %lld rows recorded, %lld more needed, capacity %lld",
+                    (long long)b->trace_rows, (long long)need, (long long)b->trace_cap);
+    DeviceGuard dg(b->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+    int64_t done = 0;
+    while (done < n) {
+        if (le > 0 && b->t % le == 0 && b->last_logged != b->t) {
+            if ((rc = batch_log(b, lbk::MODE_STEP_ENERGY))) return rc;
+            b->parity ^= 1;
+            ++b->t;
+            ++done;
+            continue;
+        }
+        int64_t run = n - done;
+        if (le > 0) {
+            const int64_t next = (b->t / le + 1) * le;
+            if (next - b->t < run) run = next - b->t;
+        }
+        hipError_t e = batch_plain(b, run);
+        if (e) return hip_fail(e, "batched step launch");
+        b->parity ^= (int)(run & 1);
+        b->t += run;
+        done += run;
+    }
+    if (le > 0 && b->t % le == 0 && b->last_logged != b->t)
+        if ((rc = batch_log(b, lbk::MODE_ENERGY))) return rc;
+    batch_sync_members(b);
+    return LB_OK;
+}
+
+int lb_batch_use_graphs(lb_batch* b, int enable)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (enable && !b->stream)
+        return fail(LB_ERR_INVALID, "the null stream cannot be captured into a graph");
+    b->use_graphs = enable != 0;
+    return LB_OK;
+}
+
+int lb_batch_member(lb_batch* b, int32_t i, lb_ctx** member)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (!member) return fail(LB_ERR_INVALID, "member is NULL");
+    if (i < 0 || i >= (int32_t)b->members.size())
+        return fail(LB_ERR_INVALID, "lattice index %d out of range", i);
+    *member = b->members[i];
+    return LB_OK;
+}
+
+int lb_batch_destroy(lb_batch* b)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!b || !g_batches.count(b)) return fail(LB_ERR_STATE, "unknown or destroyed batch");
+        g_batches.erase(b);
+    }
+    DeviceGuard dg(b->device);
+    hipError_t e = hipStreamSynchronize(b->stream);
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    for (lb_ctx* c : b->members) {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_live.erase(c);
+        delete c;
+    }
+    delete b;
     if (e) return hip_fail(e, "synchronise");
     return LB_OK;
 }

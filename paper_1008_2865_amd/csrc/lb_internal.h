@@ -43,6 +43,17 @@ struct Coef {
     uint32_t step;              // time step of the launch
 };
 
+// One lattice of a batch, as the batched kernels read it (device memory).
+struct BatchLattice {
+    Geom geom;
+    Coef coef;
+    void* buf[2];        // population buffers; the step reads buf[parity]
+    double* trace;       // this lattice's trace rows
+    double half_A1;      // (G1 + G2) / 2
+    int32_t tile_begin;  // first logical tile of this lattice in the batch
+    int32_t pad;
+};
+
 // Bytes of one stored population value.
 inline int storage_bytes(int storage)
 {
@@ -54,6 +65,11 @@ hipError_t launch_step(int storage, int mode, const void* src, void* dst,
                        hipStream_t s);
 hipError_t launch_final(const double* partials, int blocks, double t,
                         double half_A1, double* out_row, hipStream_t s);
+hipError_t launch_step_batch(int storage, int mode, int tile_x, int rows_per_iter,
+                             const BatchLattice* desc, const int32_t* tile_lattice, int tiles,
+                             int parity, uint32_t step, double* partials, hipStream_t s);
+hipError_t launch_final_batch(const BatchLattice* desc, int count, const double* partials,
+                              double t, int64_t row, hipStream_t s);
 hipError_t launch_moments(int storage, const void* src, const Geom& g,
                           const Coef& c, double* rho, double* ux, double* uy,
                           hipStream_t s);

@@ -87,15 +87,16 @@ __device__ __forceinline__ _Float16 half_stochastic(float v, uint32_t r)
 template <typename C>
 struct CoefT {
     C K1, K2, K4, K5, K8, KE0, tau, omega, sqrt_rho0, inv_rho0, rho_ref;
+    C K4x2, K8x2;   // 2 K4 and 2 K8 (the |c_x| = 2 link pairs)
     uint32_t step;  // time step of the launch (seeds the stochastic rounding)
 };
 
 template <typename C>
-CoefT<C> convert(const Coef& c)
+__host__ __device__ CoefT<C> convert(const Coef& c)
 {
     return CoefT<C>{(C)c.K1, (C)c.K2, (C)c.K4, (C)c.K5, (C)c.K8, (C)c.KE0,
                     (C)c.tau, (C)c.omega, (C)c.sqrt_rho0, (C)c.inv_rho0,
-                    (C)c.rho_ref, c.step};
+                    (C)c.rho_ref, (C)(2.0 * c.K4), (C)(2.0 * c.K8), c.step};
 }
 
 // Single-precision arithmetic uses the hardware exponential and reciprocal
@@ -105,6 +106,8 @@ CoefT<C> convert(const Coef& c)
 __device__ __forceinline__ double exp_c(double v) { return exp(v); }
 __device__ __forceinline__ float exp_c(float v) { return __expf(v); }
 __device__ __forceinline__ double rcp_c(double v) { return 1.0 / v; }
+__device__ __forceinline__ double fma_c(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fma_c(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ float rcp_c(float v) { return __builtin_amdgcn_rcpf(v); }
 
 template <typename C>
@@ -242,9 +245,10 @@ using Ic = std::integral_constant<int, J>;
 // One launch = one time step for a tile of NT columns (one lane each) by
 // tile_y rows, walked RPI rows at a time.
 template <class P, int NT, int MODE, int RPI>
-__global__ void __launch_bounds__(NT)
-k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
-       Geom g, CoefT<typename P::C> k, double* __restrict__ partials)
+__device__ __forceinline__ void
+step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
+          const Geom& g, const CoefT<typename P::C>& k, double* __restrict__ partials,
+          const int lb)
 {
     using S = typename P::S;
     using C = typename P::C;
@@ -266,7 +270,6 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wid = tid >> 6;
-    const int lb = xcd_remap(blockIdx.x, gridDim.x);
     const int sx = lb % g.tiles_x;
     const int sy = lb / g.tiles_x;
     const int x0 = sx * NT;
@@ -411,6 +414,10 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
             const C ne2 = rp2[c + 2], nw2 = rp2[c - 2], sw2 = rm2[c - 2], se2 = rm2[c + 2];
 
             if (kEnergy && own) {
+                // No contraction here: the energies must round identically
+                // in every kernel variant that computes them (the step
+                // that also logs, the energy-only pass, the batched kernel).
+#pragma clang fp contract(off)
                 const C S1 = (e1 + w1) + (n1 + s1v);
                 const C S2 = (ne + sw) + (nw + se);
                 const C S4 = (e2 + w2) + (n2 + s2v);
@@ -425,16 +432,24 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
             }
 
             if (kCollide) {
+                // Multiply-adds are written out as fma and nothing else is
+                // contracted, so every kernel variant (launch shape, batched
+                // or not) rounds each site's update identically.
+#pragma clang fp contract(off)
                 // eq. (FORCE): F = -psi(x) sum_k K_k psi(x + c_k) c_k, links
                 // paired with their opposites.
-                const C sumx = k.K1 * (e1 - w1) + k.K2 * ((ne + se) - (nw + sw)) +
-                               (C)2 * k.K4 * (e2 - w2) +
-                               k.K5 * ((C)2 * ((e2n + e2s) - (w2n + w2s)) + ((n2e + s2e) - (n2w + s2w))) +
-                               (C)2 * k.K8 * ((ne2 + se2) - (nw2 + sw2));
-                const C sumy = k.K1 * (n1 - s1v) + k.K2 * ((ne + nw) - (se + sw)) +
-                               (C)2 * k.K4 * (n2 - s2v) +
-                               k.K5 * ((C)2 * ((n2e + n2w) - (s2e + s2w)) + ((e2n + w2n) - (e2s + w2s))) +
-                               (C)2 * k.K8 * ((ne2 + nw2) - (se2 + sw2));
+                const C sumx =
+                    fma_c(k.K1, e1 - w1,
+                          fma_c(k.K2, (ne + se) - (nw + sw),
+                                fma_c(k.K4x2, e2 - w2,
+                                      fma_c(k.K5, fma_c((C)2, (e2n + e2s) - (w2n + w2s), (n2e + s2e) - (n2w + s2w)),
+                                            k.K8x2 * ((ne2 + se2) - (nw2 + sw2))))));
+                const C sumy =
+                    fma_c(k.K1, n1 - s1v,
+                          fma_c(k.K2, (ne + nw) - (se + sw),
+                                fma_c(k.K4x2, n2 - s2v,
+                                      fma_c(k.K5, fma_c((C)2, (n2e + n2w) - (s2e + s2w), (e2n + w2n) - (e2s + w2s)),
+                                            k.K8x2 * ((ne2 + nw2) - (se2 + sw2))))));
                 const C Fx = -p * sumx;
                 const C Fy = -p * sumy;
 
@@ -443,23 +458,24 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
                 const C jx = (R[1] - R[3]) + ((R[5] - R[7]) + (R[8] - R[6]));
                 const C jy = (R[2] - R[4]) + ((R[5] - R[7]) + (R[6] - R[8]));
                 const C inv = rcp_c(rho);
-                const C ux = (jx + k.tau * Fx) * inv;
-                const C uy = (jy + k.tau * Fy) * inv;
-                const C usq = (C)1.5 * (ux * ux + uy * uy);
+                const C ux = fma_c(k.tau, Fx, jx) * inv;
+                const C uy = fma_c(k.tau, Fy, jy) * inv;
+                // 1 - 1.5 u^2, and f_eq = w rho (1 - 1.5 u^2 + cu (3 + 4.5 cu)).
+                const C base = fma_c((C)-1.5, fma_c(ux, ux, uy * uy), (C)1);
                 const C r1 = rho * ((C)1 / (C)9);
                 const C r2 = rho * ((C)1 / (C)36);
                 const C om = k.omega;
-                auto axis = [&](C cu) { return r1 * ((C)1 + (C)3 * cu + (C)4.5 * cu * cu - usq); };
-                auto diag = [&](C cu) { return r2 * ((C)1 + (C)3 * cu + (C)4.5 * cu * cu - usq); };
+                auto feq = [&](C r, C cu) { return r * fma_c(cu, fma_c((C)4.5, cu, (C)3), base); };
+                auto relax = [&](C f, C fe) { return fma_c(om, fe - f, f); };
                 C* Q = q[m];
-                Q[1] = R[1] + om * (axis(ux) - R[1]);
-                Q[2] = R[2] + om * (axis(uy) - R[2]);
-                Q[3] = R[3] + om * (axis(-ux) - R[3]);
-                Q[4] = R[4] + om * (axis(-uy) - R[4]);
-                Q[5] = R[5] + om * (diag(ux + uy) - R[5]);
-                Q[6] = R[6] + om * (diag(uy - ux) - R[6]);
-                Q[7] = R[7] + om * (diag(-ux - uy) - R[7]);
-                Q[8] = R[8] + om * (diag(ux - uy) - R[8]);
+                Q[1] = relax(R[1], feq(r1, ux));
+                Q[2] = relax(R[2], feq(r1, uy));
+                Q[3] = relax(R[3], feq(r1, -ux));
+                Q[4] = relax(R[4], feq(r1, -uy));
+                Q[5] = relax(R[5], feq(r2, ux + uy));
+                Q[6] = relax(R[6], feq(r2, uy - ux));
+                Q[7] = relax(R[7], feq(r2, -ux - uy));
+                Q[8] = relax(R[8], feq(r2, ux - uy));
                 // The collision conserves mass exactly; take the rest
                 // population from that so rounding cannot drift the mass.
                 Q[0] = rho - (((Q[1] + Q[3]) + (Q[2] + Q[4])) + ((Q[5] + Q[7]) + (Q[6] + Q[8])));
@@ -537,11 +553,42 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
     }
 }
 
+// One launch = one time step of one lattice: workgroup b updates logical
+// tile xcd_remap(b).
+template <class P, int NT, int MODE, int RPI>
+__global__ void __launch_bounds__(NT)
+k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
+       Geom g, CoefT<typename P::C> k, double* __restrict__ partials)
+{
+    step_tile<P, NT, MODE, RPI>(src, dst, g, k, partials, xcd_remap(blockIdx.x, gridDim.x));
+}
+
+// One launch = one time step of a batch of independent lattices.  The
+// logical tiles of all lattices are numbered consecutively (lattice by
+// lattice); tile_lattice maps a logical tile to its lattice, whose
+// geometry, coefficients and buffers sit in desc.  Every lattice's tile is
+// processed exactly as the single-lattice kernel processes it, so fields
+// are bit-identical to single-lattice runs with the same tile shape.
+template <class P, int NT, int MODE, int RPI>
+__global__ void __launch_bounds__(NT)
+k_step_batch(const BatchLattice* __restrict__ desc, const int32_t* __restrict__ tile_lattice,
+             int parity, uint32_t step, double* __restrict__ partials)
+{
+    using S = typename P::S;
+    const int gl = xcd_remap(blockIdx.x, gridDim.x);
+    const int lat = tile_lattice[gl];
+    const BatchLattice& d = desc[lat];
+    CoefT<typename P::C> k = convert<typename P::C>(d.coef);
+    k.step = step;
+    step_tile<P, NT, MODE, RPI>(static_cast<const S*>(d.buf[parity]),
+                                static_cast<S*>(d.buf[parity ^ 1]), d.geom, k,
+                                partials + (int64_t)d.tile_begin * 4, gl - d.tile_begin);
+}
+
 // Fixed-order reduction of the per-workgroup partials into one trace row
-// {t, M, E_s, E_m, sum psi^2, E_bulk}.
-__global__ void __launch_bounds__(256)
-k_final(const double* __restrict__ partials, int blocks, double t,
-        double half_A1, double* __restrict__ out)
+// {t, M, E_s, E_m, sum psi^2, E_bulk} (one workgroup of 256 threads).
+__device__ __forceinline__ void final_row(const double* __restrict__ partials, int blocks,
+                                          double t, double half_A1, double* __restrict__ out)
 {
     __shared__ double sm[4][256];
     const int tid = threadIdx.x;
@@ -567,6 +614,23 @@ k_final(const double* __restrict__ partials, int blocks, double t,
         out[4] = sm[3][0];
         out[5] = half_A1 * sm[3][0];
     }
+}
+
+__global__ void __launch_bounds__(256)
+k_final(const double* __restrict__ partials, int blocks, double t, double half_A1,
+        double* __restrict__ out)
+{
+    final_row(partials, blocks, t, half_A1, out);
+}
+
+// One workgroup per lattice of a batch: row `row` of each lattice's trace.
+__global__ void __launch_bounds__(256)
+k_final_batch(const BatchLattice* __restrict__ desc, const double* __restrict__ partials,
+              double t, int64_t row)
+{
+    const BatchLattice& d = desc[blockIdx.x];
+    final_row(partials + (int64_t)d.tile_begin * 4, d.geom.blocks, t, d.half_A1,
+              d.trace + row * 6);
 }
 
 // rho and u = j / rho of the pre-collision state, dense [ny][nx] doubles.
@@ -684,7 +748,64 @@ hipError_t step_p(int mode, const void* src, void* dst, const Geom& g,
     }
 }
 
+struct BatchLaunch {
+    const BatchLattice* desc;
+    const int32_t* tile_lattice;
+    int tiles;
+    int parity;
+    uint32_t step;
+    double* partials;
+};
+
+template <class P, int NT, int RPI>
+hipError_t batch_nt(int mode, const BatchLaunch& a, hipStream_t s)
+{
+    const dim3 grid(a.tiles), block(NT);
+    if (mode == MODE_STEP)
+        hipLaunchKernelGGL((k_step_batch<P, NT, MODE_STEP, RPI>), grid, block, 0, s, a.desc,
+                           a.tile_lattice, a.parity, a.step, a.partials);
+    else if (mode == MODE_STEP_ENERGY)
+        hipLaunchKernelGGL((k_step_batch<P, NT, MODE_STEP_ENERGY, RPI>), grid, block, 0, s, a.desc,
+                           a.tile_lattice, a.parity, a.step, a.partials);
+    else
+        hipLaunchKernelGGL((k_step_batch<P, NT, MODE_ENERGY, RPI>), grid, block, 0, s, a.desc,
+                           a.tile_lattice, a.parity, a.step, a.partials);
+    return hipGetLastError();
+}
+
+template <class P>
+hipError_t batch_p(int mode, int tile_x, int rpi, const BatchLaunch& a, hipStream_t s)
+{
+    const bool two = rpi == 2;
+    switch (tile_x) {
+    case 64: return two ? batch_nt<P, 64, 2>(mode, a, s) : batch_nt<P, 64, 1>(mode, a, s);
+    case 128: return two ? batch_nt<P, 128, 2>(mode, a, s) : batch_nt<P, 128, 1>(mode, a, s);
+    case 256: return two ? batch_nt<P, 256, 2>(mode, a, s) : batch_nt<P, 256, 1>(mode, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 }  // namespace
+
+hipError_t launch_step_batch(int storage, int mode, int tile_x, int rows_per_iter,
+                             const BatchLattice* desc, const int32_t* tile_lattice, int tiles,
+                             int parity, uint32_t step, double* partials, hipStream_t s)
+{
+    const BatchLaunch a{desc, tile_lattice, tiles, parity, step, partials};
+    switch (storage) {
+    case ST_F64: return batch_p<PF64>(mode, tile_x, rows_per_iter, a, s);
+    case ST_F32: return batch_p<PF32>(mode, tile_x, rows_per_iter, a, s);
+    case ST_F16DEV: return batch_p<PF16>(mode, tile_x, rows_per_iter, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_final_batch(const BatchLattice* desc, int count, const double* partials,
+                              double t, int64_t row, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_final_batch, dim3(count), dim3(256), 0, s, desc, partials, t, row);
+    return hipGetLastError();
+}
 
 hipError_t launch_step(int storage, int mode, const void* src, void* dst,
                        const Geom& g, const Coef& c, double* partials,

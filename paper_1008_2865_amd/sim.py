@@ -117,3 +117,90 @@ class LBSim:
             self.close()
         except Exception:
             pass
+
+
+class _Member(LBSim):
+    """A lattice owned by an LBBatch: observables and state export only."""
+
+    def __init__(self, batch, i, nx, ny, storage, trace_cap):
+        self.torch = batch.torch
+        self.ctx = B.lb_batch_member(batch.b, i)
+        self.nx, self.ny, self.storage, self.trace_cap = nx, ny, storage, trace_cap
+        self._batch = batch
+
+    def step(self, n=1):
+        raise RuntimeError("step the whole batch with LBBatch.step")
+
+    def close(self):
+        self.ctx = None
+
+
+class LBBatch:
+    """Many independent periodic lattices advanced by one launch per step.
+
+    ``lattices`` is a list of dicts with keys rho_init (ny, nx) and G1, G2
+    (optionally tau, rho0, tile_y, rho_ref).  Shared settings (storage,
+    tile_x, tile_rows, log_every, trace_cap) are keyword arguments.  Plain
+    steps are captured into HIP graphs when the current torch stream is not
+    the null stream.
+    """
+
+    def __init__(self, lattices, *, storage="f32", tile_x=0, tile_rows=0, log_every=0,
+                 trace_cap=None, max_steps=None, use_graphs=True):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("LBBatch needs a HIP device")
+        self.torch = torch
+        if trace_cap is None:
+            trace_cap = (max_steps // log_every + 2) if (log_every and max_steps) else (
+                1024 if log_every else 0)
+        st = STORAGE[storage]
+        self.params, rhos, self.shapes = [], [], []
+        for L in lattices:
+            rho = np.ascontiguousarray(L["rho_init"], dtype=np.float64)
+            ny, nx = rho.shape
+            self.params.append(B.make_params(
+                nx, ny, storage=st, tau=L.get("tau", 1.0), rho0=L.get("rho0", 1.0),
+                G1=L["G1"], G2=L["G2"], log_every=log_every, trace_cap=trace_cap,
+                tile_x=tile_x, tile_y=L.get("tile_y", 0), tile_rows=tile_rows,
+                rho_ref=L.get("rho_ref", float(rho.mean())) if st == B.LB_F16DEV else 0.0))
+            rhos.append(rho)
+            self.shapes.append((ny, nx))
+        nbytes = B.lb_batch_workspace_bytes(self.params)
+        if nbytes == 0:
+            for p in self.params:
+                B._check(B.lb_validate(p))
+            raise B.LBError(B.LB_ERR_INVALID, B.lb_last_error())
+        self.stream = torch.cuda.current_stream()
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        self.b = B.lb_batch_init(self.params, self.workspace, nbytes, rhos,
+                                 stream=self.stream.cuda_stream)
+        if not use_graphs or self.stream.cuda_stream == 0:
+            if self.stream.cuda_stream != 0:
+                B.lb_batch_use_graphs(self.b, False)
+        self.members = [_Member(self, i, nx, ny, storage, trace_cap)
+                        for i, (ny, nx) in enumerate(self.shapes)]
+        self.sites = sum(nx * ny for ny, nx in self.shapes)
+
+    def step(self, n=1):
+        B.lb_batch_step(self.b, n)
+
+    def __getitem__(self, i):
+        return self.members[i]
+
+    def __len__(self):
+        return len(self.members)
+
+    def close(self):
+        if getattr(self, "b", None):
+            for m in self.members:
+                m.close()
+            B.lb_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -136,3 +136,16 @@ def test_init_without_device_reports_hip_error():
     with pytest.raises(B.LBError) as e:
         P.lb_init(p, 256, P.lb_workspace_bytes(p), np.full((8, 8), 0.7))
     assert e.value.code == B.LB_ERR_HIP
+
+
+def test_batch_rejects_mismatched_settings():
+    # Lattices of a batch must share storage, tile_x, tile_rows, log_every
+    # and trace_cap; sizes and couplings may differ.
+    ok = [B.make_params(64, 64, tile_x=64), B.make_params(100, 70, tile_x=64, G2=0.3)]
+    assert B.lb_batch_workspace_bytes(ok) > sum(P.lb_workspace_bytes(p) for p in ok)
+    for bad in ([B.make_params(64, 64, tile_x=64), B.make_params(64, 64, tile_x=128)],
+                [B.make_params(64, 64, tile_x=64), B.make_params(64, 64, tile_x=64, log_every=3)],
+                [B.make_params(64, 64, tile_x=64), B.make_params(64, 64, tile_x=64, storage=P.LB_F64)],
+                [B.make_params(64, 64, tile_x=64), B.make_params(4, 64, tile_x=64)]):
+        assert B.lb_batch_workspace_bytes(bad) == 0
+        assert P.lb_last_error()

@@ -239,20 +239,23 @@ def bench_batch(args):
     K = args.steps if args.steps != 20000 else 10000
     W, le = args.warmup, args.log_every
     spec = inputs.batched_lattices()
-    shapes = [(d["n"], d["n"]) for d in spec]
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
-        tx, tr, per = autotune.tune_batch(shapes, args.storage)
         lats = []
         for d in spec:
             G1, G2 = inputs.couplings(d["r"])
-            lats.append(dict(rho_init=inputs.rho_noise(d["n"], d["n"], d["seed"]), G1=G1, G2=G2,
-                             tile_y=per[(d["n"], d["n"])]))
+            lats.append(dict(rho_init=inputs.rho_noise(d["n"], d["n"], d["seed"]), G1=G1, G2=G2))
+        if args.tile_y:
+            tx, tr, ty = args.tile_x or 128, args.tile_rows or 1, args.tile_y
+        else:
+            tx, tr, ty = autotune.tune_batch(lats, args.storage)
+        for L in lats:
+            L["tile_y"] = ty
         batch = LBBatch(lats, storage=args.storage, tile_x=tx, tile_rows=tr, log_every=le,
                         max_steps=W + K + le)
         sites = batch.sites
-        log(f"bench: batch of {len(lats)} lattices, {sites} sites, tile_x {tx}, rows/stage {tr}, "
-            f"tile_y {sorted(set(per.values()))}, warmup {W}, steps {K}, log every {le}")
+        log(f"bench: batch of {len(lats)} lattices, {sites} sites, tile {tx}x{ty}x{tr}, "
+            f"warmup {W}, steps {K}, log every {le}")
 
         def run(nsteps, pairs=None):
             done = 0
@@ -297,8 +300,7 @@ def bench_batch(args):
                         f"sizes U{{128..1024}}^2, G2/|G1| ~ U[0, 0.15] each at A1=-4.9, own seed "
                         f"each (master seed 4), {args.storage}, one launch per step for all "
                         f"lattices, plain steps replayed from HIP graphs, pseudo-energy every {le}",
-            "lattices": len(lats), "sites": sites, "tile_x": tx, "tile_rows": tr,
-            "tile_y_by_size": {str(k[0]): v for k, v in sorted(per.items())},
+            "lattices": len(lats), "sites": sites, "tile_x": tx, "tile_y": ty, "tile_rows": tr,
         },
         "effective_gbps": round(value * bpl / 1e3, 1),
         "roofline": {

@@ -10,6 +10,8 @@ not change the computed fields.
 import json
 import os
 
+import numpy as np
+
 DEFAULT_CANDIDATES = [(256, 32, 1), (256, 16, 1), (128, 32, 1), (256, 32, 2), (128, 16, 1),
                       (64, 32, 1), (256, 64, 2)]
 
@@ -80,28 +82,48 @@ def tune(nx, ny, storage="f32", candidates=None, refresh=False, steps=100):
     return best[1], best[2], best[3]
 
 
-def tune_batch(shapes, storage="f32", tile_x=None, tile_rows=1, tile_ys=(8, 16, 32, 64),
-               refresh=False, steps=100):
-    """Shared (tile_x, tile_rows) and a tile_y per distinct (ny, nx) for a
-    batch: tile_x is the widest strip every lattice fills unless given;
-    tile_y is tuned per size with that strip width."""
+def tune_batch(lattices, storage="f32", tile_x=None, tile_ys=(8, 16, 32, 64), tile_rows=(1, 2),
+               refresh=False, steps=40):
+    """Shared (tile_x, tile_rows, tile_y) for a batch, timed on the whole
+    batch (one launch covers every lattice, so the batch's own parallelism,
+    not a single lattice's, decides the best tile height).  ``lattices``
+    are LBBatch lattice dicts; tile_x defaults to the widest strip every
+    lattice fills."""
+    import hashlib
+
+    import torch
+
+    from .sim import LBBatch
+
+    shapes = [tuple(np.shape(L["rho_init"])) for L in lattices]
     if tile_x is None:
         m = min(nx for _, nx in shapes)
         tile_x = 256 if m >= 256 else 128 if m >= 128 else 64
+    sig = hashlib.sha1(repr(sorted(shapes)).encode()).hexdigest()[:12]
+    key = f"batch:{storage}:{len(shapes)}:{sig}:x{tile_x}"
     cache = _load()
-    per = {}
-    for ny, nx in sorted(set(map(tuple, shapes))):
-        key = f"{storage}:{nx}x{ny}:x{tile_x}:r{tile_rows}"
-        if not refresh and key in cache:
-            per[(ny, nx)] = cache[key]["tile_y"]
+    if not refresh and key in cache:
+        c = cache[key]
+        return c["tile_x"], c["tile_rows"], c["tile_y"]
+    best = None
+    for tr in tile_rows:
+        if storage == "f64" and tr != 1:
             continue
-        best = None
         for ty in tile_ys:
-            ty = min(ty, ny)
-            us = time_shape(nx, ny, storage, tile_x, ty, tile_rows, steps=steps)
+            lats = [dict(L, tile_y=min(ty, sh[0])) for L, sh in zip(lattices, shapes)]
+            batch = LBBatch(lats, storage=storage, tile_x=tile_x, tile_rows=tr)
+            batch.step(10)
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            batch.step(steps)
+            b.record()
+            torch.cuda.synchronize()
+            us = a.elapsed_time(b) * 1e3 / steps
+            batch.close()
+            del batch
             if best is None or us < best[0]:
-                best = (us, ty)
-        cache[key] = {"tile_y": best[1], "us_per_step": best[0]}
-        per[(ny, nx)] = best[1]
+                best = (us, ty, tr)
+    cache[key] = {"tile_x": tile_x, "tile_rows": best[2], "tile_y": best[1], "us_per_step": best[0]}
     _save(cache)
-    return tile_x, tile_rows, per
+    return tile_x, best[2], best[1]

@@ -97,9 +97,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=None)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a device copy of one population buffer (counter calibration)")
-    ap.add_argument("--workload", default="single", choices=["single", "batch"],
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "adjoint"],
                     help="single: one lattice (default, the headline workload); batch: the "
-                         "96-lattice sweep of independent lattices")
+                         "96-lattice sweep of independent lattices; adjoint: gradients of the "
+                         "droplet functional at 512^2 (adjoint/forward time ratio)")
+    ap.add_argument("--checkpoint-every", type=int, default=100)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -121,6 +123,8 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "adjoint":
+        return bench_adjoint(args)
     n, K, W, le = args.n, args.steps, args.warmup, args.log_every
     G1, G2 = inputs.couplings(args.r)
     rho0 = inputs.rho_noise(n, n, args.seed)
@@ -330,6 +334,72 @@ def bench_batch(args):
             "cores": O.threads(), "kind": "oracle",
             "sample": f"largest lattice of the batch ({d['n']}x{d['n']}), FP64 oracle, {steps} steps, "
                       f"{dt:.1f} s wall"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_adjoint(args):
+    """Gradients of L = (E(T) - E*)^2 + beta A(T) on a 512^2 lattice (r = 0.1,
+    seed 1, FP32, T = 3000 steps, a checkpoint every 100 steps, E* = 1.01 E(T)
+    of the same run, beta = 1/512^2, eps = 1e-6): wall time of the forward
+    pass (T steps plus checkpoint copies and the loss) and of the backward
+    pass (recomputation of every segment, tape, adjoint steps, gradients)."""
+    import torch
+
+    from paper_1008_2865_amd import inputs
+    from paper_1008_2865_amd.adjoint import DropletLoss
+
+    n = args.n if args.n != 2048 else 512
+    T = args.steps if args.steps != 20000 else 3000
+    reps = 3
+    G1, G2 = inputs.couplings(args.r)
+    rho = inputs.rho_noise(n, n, args.seed)
+    dl = DropletLoss(n, n, T, E_target=0.0, beta=1.0 / n ** 2, eps=1e-6, storage=args.storage,
+                     checkpoint_every=args.checkpoint_every, tile_x=args.tile_x,
+                     tile_y=args.tile_y, tile_rows=args.tile_rows)
+    log(f"bench: adjoint {n}x{n} {args.storage}, T {T}, checkpoint every {args.checkpoint_every}")
+    dl.E_target = 1.01 * dl.forward(rho, G1, G2)[1]
+    dl.backward()  # warm-up pass
+    torch.cuda.synchronize()
+    fw, bw = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        L, E, A, M = dl.forward(rho, G1, G2)
+        t1 = time.perf_counter()
+        dG1, dG2, drho = dl.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fw.append(t1 - t0)
+        bw.append(t2 - t1)
+        log(f"bench: forward {fw[-1] * 1e3:.1f} ms, backward {bw[-1] * 1e3:.1f} ms")
+    dl.close()
+    f_s, b_s = min(fw), min(bw)
+    out = {
+        "metric": "adjoint/forward wall-time ratio (droplet functional gradients)",
+        "value": round(b_s / f_s, 3), "unit": "x", "n_gpus": 1, "steps": T, "warmup": 1,
+        "ms_per_step": round((f_s + b_s) * 1e3 / T, 6), "higher_is_better": False,
+        "scaling": "weak", "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
+        "config": {
+            "workload": f"adjoint of a {n}x{n} periodic two-belt D2Q9 run, r={args.r}, seed "
+                        f"{args.seed}, {args.storage}, T={T}, checkpoint every "
+                        f"{args.checkpoint_every}, L=(E(T)-1.01 E_ref)^2 + A(T)/{n}^2",
+        },
+        "forward_ms": round(f_s * 1e3, 3), "backward_ms": round(b_s * 1e3, 3),
+        "forward_mlups": round(n * n * T / f_s / 1e6, 1),
+        "gradient_mlups": round(n * n * T / (f_s + b_s) / 1e6, 1),
+        "loss": [L, E, A, M], "dG": [dG1, dG2], "drho_l2": float(torch.linalg.norm(drho)),
+    }
+    if args.cpu_seconds > 0 or args.cpu_steps:
+        log("bench: timing the oracle gradient on a bounded sample ...")
+        from oracle import adjoint as OA
+
+        steps = args.cpu_steps or 20
+        t0 = time.perf_counter()
+        OA.loss_and_grads(rho, G1, G2, steps, 1.0, 1.01 * E, 1.0 / n ** 2, 1e-6)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {
+            "value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS (forward + gradient)",
+            "cores": torch.get_num_threads(), "kind": "oracle",
+            "sample": f"{n}x{n}, {steps} steps, FP64 autograd oracle, {dt:.1f} s wall"}
     print(json.dumps(out), flush=True)
 
 

@@ -214,6 +214,59 @@ int lb_batch_member(lb_batch* b, int32_t i, lb_ctx** member);
 /* Release the batch and its member contexts (after synchronising). */
 int lb_batch_destroy(lb_batch* b);
 
+/* ---------------------------------------------------------------------------
+ * Adjoint: gradients of a functional of the state after T steps of eq. (1)
+ * from a fluid at rest (section IV start: f_i = w_i rho_init),
+ *   L = (E(T) - E_target)^2 + beta * A(T),
+ *   E = E_s + E_m (section V, as lb_pseudo_energy),
+ *   A = sum_x sqrt(D_x rho^2 + D_y rho^2 + eps^2), D the central difference
+ *       (x+1 minus x-1, halved): a measure of interface length,
+ * with respect to G1, G2 and rho_init, by reverse-mode differentiation of
+ * the discrete step (the transposed collision, force and streaming).  The
+ * forward run keeps a copy of the populations every checkpoint_every steps;
+ * the backward pass recomputes each segment from its copy, recording
+ * (rho, j, psi) of every state, and steps the adjoint back through it.
+ * Storage must be LB_F64 or LB_F32 (the arithmetic precision of both
+ * passes; global sums in double); log_every and trace_cap are ignored.
+ * Workspace and stream rules are those of lb_init.
+ * ------------------------------------------------------------------------ */
+typedef struct lb_adj lb_adj;
+
+typedef struct lb_adj_loss {
+    double E_target;  /* E* of the energy term                              */
+    double beta;      /* weight of the interface measure                     */
+    double eps;       /* regularisation of |grad rho| in A, > 0              */
+} lb_adj_loss;
+
+/* Workspace bytes for T = nsteps >= 0 steps with a checkpoint every
+ * checkpoint_every >= 1 steps (about ceil(T/every) population copies plus
+ * `every` tape entries of 4 values per site), or 0 if invalid. */
+size_t lb_adj_workspace_bytes(const lb_params* p, int64_t nsteps,
+                              int32_t checkpoint_every);
+
+/* Create an adjoint context.  p's tau, rho0, sizes, storage and launch
+ * shape are used; G1 and G2 are given to each lb_adj_forward. */
+int lb_adj_init(lb_adj** out, const lb_params* p, int64_t nsteps,
+                int32_t checkpoint_every, void* workspace, size_t bytes,
+                void* hip_stream);
+
+/* Run T steps from f_i = w_i rho_init (ny*nx doubles, finite and > 0, host
+ * or device memory per on_device) with couplings G1, G2 and evaluate the
+ * loss: out = {L, E(T), A(T), M(T) = sum rho}.  Synchronous.
+ * LB_ERR_NONFINITE if L or M is not finite. */
+int lb_adj_forward(lb_adj* a, const double* rho_init, int on_device,
+                   double G1, double G2, const lb_adj_loss* loss,
+                   double out[4]);
+
+/* Gradients of the loss of the last successful lb_adj_forward:
+ * dG = {dL/dG1, dL/dG2} (host) and drho = dL/drho_init (ny*nx doubles, a
+ * device pointer if on_device = 1, else host memory).  Synchronous; may be
+ * called repeatedly.  LB_ERR_STATE without a successful forward. */
+int lb_adj_backward(lb_adj* a, double dG[2], double* drho, int on_device);
+
+/* Release the adjoint context (after synchronising its stream). */
+int lb_adj_destroy(lb_adj* a);
+
 #ifdef __cplusplus
 }
 #endif

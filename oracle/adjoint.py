@@ -94,5 +94,5 @@ def loss_and_grads(rho_init, G1, G2, steps, tau, E_target, beta, eps, rho0=1.0):
     g2 = torch.tensor(float(G2), dtype=torch.float64, requires_grad=True)
     L, f, E = loss(r, g1, g2, steps, tau, E_target, beta, eps, rho0)
     L.backward()
-    return (float(L), float(g1.grad), float(g2.grad), r.grad.numpy().copy(), float(E),
+    return (float(L.detach()), float(g1.grad), float(g2.grad), r.grad.numpy().copy(), float(E.detach()),
             f.detach().numpy())

@@ -40,6 +40,11 @@ class lb_params(ctypes.Structure):
                 ("rho_ref", ctypes.c_double)]
 
 
+class lb_adj_loss(ctypes.Structure):
+    _fields_ = [("E_target", ctypes.c_double), ("beta", ctypes.c_double),
+                ("eps", ctypes.c_double)]
+
+
 _vp = ctypes.c_void_p
 _P = ctypes.POINTER(lb_params)
 
@@ -67,6 +72,13 @@ SIGNATURES = {
     "lb_batch_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lb_batch_member": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]),
     "lb_batch_destroy": (ctypes.c_int, [_vp]),
+    "lb_adj_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int64, ctypes.c_int32]),
+    "lb_adj_init": (ctypes.c_int, [ctypes.POINTER(_vp), _P, ctypes.c_int64, ctypes.c_int32, _vp,
+                                   ctypes.c_size_t, _vp]),
+    "lb_adj_forward": (ctypes.c_int, [_vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                      ctypes.POINTER(lb_adj_loss), _vp]),
+    "lb_adj_backward": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
+    "lb_adj_destroy": (ctypes.c_int, [_vp]),
 }
 
 _lib = None
@@ -217,3 +229,34 @@ def lb_batch_member(b, i):
 
 def lb_batch_destroy(b):
     return _check(lib().lb_batch_destroy(b))
+
+
+def lb_adj_workspace_bytes(p, nsteps, checkpoint_every):
+    return lib().lb_adj_workspace_bytes(ctypes.byref(p), nsteps, checkpoint_every)
+
+
+def lb_adj_init(p, nsteps, checkpoint_every, workspace, nbytes, stream=0):
+    a = _vp()
+    _check(lib().lb_adj_init(ctypes.byref(a), ctypes.byref(p), nsteps, checkpoint_every,
+                             _ptr(workspace), nbytes, stream or None))
+    return a.value
+
+
+def lb_adj_forward(a, rho_init, G1, G2, E_target, beta, eps, on_device=False):
+    """(L, E(T), A(T), M(T))."""
+    out = (ctypes.c_double * 4)()
+    loss = lb_adj_loss(E_target=E_target, beta=beta, eps=eps)
+    _check(lib().lb_adj_forward(a, _ptr(rho_init), int(bool(on_device)), G1, G2,
+                                ctypes.byref(loss), out))
+    return tuple(out)
+
+
+def lb_adj_backward(a, drho, on_device=False):
+    """(dL/dG1, dL/dG2); dL/drho_init is written into drho."""
+    dG = (ctypes.c_double * 2)()
+    _check(lib().lb_adj_backward(a, dG, _ptr(drho), int(bool(on_device))))
+    return dG[0], dG[1]
+
+
+def lb_adj_destroy(a):
+    return _check(lib().lb_adj_destroy(a))

@@ -132,10 +132,20 @@ Geom make_geom(const lb_params& p)
     if ((g.pitch / 64) % 2 == 0) g.pitch += 64;  // pitch <= nx + 127
     g.plane = (int64_t)p.ny * g.pitch;
     g.tile_x = p.tile_x ? p.tile_x : (p.nx >= 256 ? 256 : p.nx >= 128 ? 128 : 64);
-    g.tile_y = p.tile_y ? p.tile_y : 32;
+    g.tiles_x = (p.nx + g.tile_x - 1) / g.tile_x;
+    if (p.tile_y) {
+        g.tile_y = p.tile_y;
+    } else {
+        // The tallest tile of 32, 16, 8, 4 or 2 rows that still gives at
+        // least 512 workgroups (two per CU): tall tiles re-read fewer halo
+        // rows, but a lattice of a few hundred rows would otherwise leave
+        // most of the 256 CUs idle.
+        g.tile_y = 32;
+        while (g.tile_y > 2 && (int64_t)g.tiles_x * ((p.ny + g.tile_y - 1) / g.tile_y) < 512)
+            g.tile_y /= 2;
+    }
     if (g.tile_y > p.ny) g.tile_y = p.ny;
     g.rows_per_iter = p.tile_rows ? p.tile_rows : 1;
-    g.tiles_x = (p.nx + g.tile_x - 1) / g.tile_x;
     g.blocks = g.tiles_x * ((p.ny + g.tile_y - 1) / g.tile_y);
     return g;
 }
@@ -889,6 +899,328 @@ int lb_batch_destroy(lb_batch* b)
     delete b;
     if (e) return hip_fail(e, "synchronise");
     return LB_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Adjoint of a run: gradients of L = (E(T) - E*)^2 + beta A(T).
+// ---------------------------------------------------------------------------
+struct lb_adj {
+    lb_ctx* fwd;          // the forward lattice (never handed out)
+    lbk::AdjParams ap;
+    int64_t T;
+    int32_t every, nseg;
+    size_t ckpt_bytes;    // one raw population buffer
+    char* ckpt;           // nseg checkpoints, at t = 0, every, 2 every, ...
+    char* tape;           // `every` tape entries of 4 N values
+    char* tapeT;          // tape entry of the state at T
+    char* lam[2];         // 9 N values each
+    char* g[2];           // N values each
+    char* gF;             // 2 N values
+    char* dir;            // 2 N values
+    double* part;         // adj_blocks x 2: dL/dG from the steps
+    double* partE;        // adj_blocks x 2: dE/dG at T
+    double* partA;        // adj_blocks: interface measure
+    double* red;          // 8 reduced values
+    double* drho;         // N doubles
+    int blocks;
+    int32_t tape_seg;     // segment whose tape the tape region holds, or -1
+    bool have_forward;
+    double E, A, E_target, beta, eps;
+};
+
+namespace {
+
+std::set<lb_adj*> g_adjs;
+
+// n steps of the forward lattice, each also recording the tape entry of
+// the state it leaves (entry j = state t + j).
+int adj_tape_steps(lb_adj* a, int64_t n)
+{
+    lb_ctx* c = a->fwd;
+    const size_t entry = (size_t)4 * c->p.nx * c->p.ny * (a->ap.f64 ? 8 : 4);
+    for (int64_t j = 0; j < n; ++j) {
+        c->coef.step = (uint32_t)c->t;
+        hipError_t e = lbk::launch_step(c->p.storage, lbk::MODE_STEP_TAPE, c->buf[c->cur],
+                                        c->buf[c->cur ^ 1], c->g, c->coef,
+                                        reinterpret_cast<double*>(a->tape + j * entry), c->stream);
+        if (e) return hip_fail(e, "step kernel launch");
+        c->cur ^= 1;
+        ++c->t;
+    }
+    return LB_OK;
+}
+
+int check_adj(lb_adj* a)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!a || !g_adjs.count(a)) return fail(LB_ERR_STATE, "unknown or destroyed adjoint context");
+    return LB_OK;
+}
+
+struct AdjLayout {
+    lb_params fp;         // forward parameters: no trace
+    size_t fwd, fwd_bytes, ckpt, ckpt_bytes, tape, tapeT, lam[2], g[2], gF, dir, part, partE, partA,
+        red, drho, total;
+    int32_t nseg;
+    int blocks;
+};
+
+int adj_layout(const lb_params* p, int64_t nsteps, int32_t every, AdjLayout* L)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (p->storage != LB_F64 && p->storage != LB_F32)
+        return fail(LB_ERR_INVALID, "the adjoint needs LB_F64 or LB_F32 storage");
+    if (nsteps < 0) return fail(LB_ERR_INVALID, "nsteps must be >= 0");
+    if (every < 1) return fail(LB_ERR_INVALID, "checkpoint_every must be >= 1");
+    L->fp = *p;
+    L->fp.log_every = 0;
+    L->fp.trace_cap = 0;
+    const Geom g = make_geom(L->fp);
+    const Layout F = make_layout(L->fp, g);
+    const int64_t N = (int64_t)p->nx * p->ny;
+    const size_t es = p->storage == LB_F64 ? 8 : 4;
+    const int64_t nseg = (nsteps + every - 1) / every;
+    if (nseg > INT32_MAX) return fail(LB_ERR_INVALID, "too many checkpoints");
+    L->nseg = (int32_t)nseg;
+    L->blocks = lbk::adj_blocks(N);
+    const int64_t seg_len = nsteps < every ? nsteps : every;
+    size_t off = 0;
+    L->fwd = off; L->fwd_bytes = F.total; off += align_up(F.total);
+    L->ckpt_bytes = (size_t)9 * g.plane * es;
+    L->ckpt = off; off += (size_t)nseg * align_up(L->ckpt_bytes);
+    L->tape = off; off += align_up((size_t)seg_len * 4 * N * es);
+    L->tapeT = off; off += align_up((size_t)4 * N * es);
+    for (int q = 0; q < 2; ++q) { L->lam[q] = off; off += align_up((size_t)9 * N * es); }
+    for (int q = 0; q < 2; ++q) { L->g[q] = off; off += align_up((size_t)N * es); }
+    L->gF = off; off += align_up((size_t)2 * N * es);
+    L->dir = off; off += align_up((size_t)2 * N * es);
+    L->part = off; off += align_up((size_t)L->blocks * 2 * sizeof(double));
+    L->partE = off; off += align_up((size_t)L->blocks * 2 * sizeof(double));
+    L->partA = off; off += align_up((size_t)L->blocks * sizeof(double));
+    L->red = off; off += align_up(8 * sizeof(double));
+    L->drho = off; off += align_up((size_t)N * sizeof(double));
+    L->total = off;
+    return LB_OK;
+}
+
+}  // namespace
+
+size_t lb_adj_workspace_bytes(const lb_params* p, int64_t nsteps, int32_t checkpoint_every)
+{
+    AdjLayout L;
+    return adj_layout(p, nsteps, checkpoint_every, &L) ? 0 : L.total;
+}
+
+int lb_adj_init(lb_adj** out, const lb_params* p, int64_t nsteps, int32_t checkpoint_every,
+                void* workspace, size_t bytes, void* hip_stream)
+{
+    if (!out) return fail(LB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    AdjLayout L;
+    int rc = adj_layout(p, nsteps, checkpoint_every, &L);
+    if (rc) return rc;
+    if (!workspace) return fail(LB_ERR_INVALID, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(LB_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
+    if (bytes < L.total) return fail(LB_ERR_INVALID, "workspace too small: %zu < %zu bytes", bytes, L.total);
+    char* ws = static_cast<char*>(workspace);
+    const std::vector<double> ones((size_t)p->nx * p->ny, 1.0);
+    lb_ctx* c = nullptr;
+    if ((rc = lb_init(&c, &L.fp, ws + L.fwd, L.fwd_bytes, ones.data(), nullptr, nullptr, 0, hip_stream)))
+        return rc;
+    lb_adj* a = new lb_adj();
+    a->fwd = c;
+    a->ap.nx = p->nx;
+    a->ap.ny = p->ny;
+    a->ap.f64 = p->storage == LB_F64;
+    a->ap.G1 = p->G1;
+    a->ap.G2 = p->G2;
+    a->ap.tau = p->tau;
+    a->ap.sqrt_rho0 = std::sqrt(p->rho0);
+    a->ap.inv_rho0 = 1.0 / p->rho0;
+    a->T = nsteps;
+    a->every = checkpoint_every;
+    a->nseg = L.nseg;
+    a->ckpt_bytes = L.ckpt_bytes;
+    a->ckpt = ws + L.ckpt;
+    a->tape = ws + L.tape;
+    a->tapeT = ws + L.tapeT;
+    for (int q = 0; q < 2; ++q) {
+        a->lam[q] = ws + L.lam[q];
+        a->g[q] = ws + L.g[q];
+    }
+    a->gF = ws + L.gF;
+    a->dir = ws + L.dir;
+    a->part = reinterpret_cast<double*>(ws + L.part);
+    a->partE = reinterpret_cast<double*>(ws + L.partE);
+    a->partA = reinterpret_cast<double*>(ws + L.partA);
+    a->red = reinterpret_cast<double*>(ws + L.red);
+    a->drho = reinterpret_cast<double*>(ws + L.drho);
+    a->blocks = L.blocks;
+    a->tape_seg = -1;
+    a->have_forward = false;
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_adjs.insert(a);
+    }
+    *out = a;
+    return LB_OK;
+}
+
+int lb_adj_forward(lb_adj* a, const double* rho_init, int on_device, double G1, double G2,
+                   const lb_adj_loss* loss, double out[4])
+{
+    int rc = check_adj(a);
+    if (rc) return rc;
+    if (!rho_init || !loss || !out) return fail(LB_ERR_INVALID, "NULL argument");
+    if (!std::isfinite(G1) || !std::isfinite(G2)) return fail(LB_ERR_INVALID, "G1, G2 must be finite");
+    if (!std::isfinite(loss->E_target) || !std::isfinite(loss->beta) || !std::isfinite(loss->eps) ||
+        !(loss->eps > 0.0))
+        return fail(LB_ERR_INVALID, "loss: E_target and beta must be finite, eps finite and > 0");
+    lb_ctx* c = a->fwd;
+    DeviceGuard dg(c->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+    const int64_t N = (int64_t)c->p.nx * c->p.ny;
+    hipStream_t st = c->stream;
+    hipError_t e;
+    // Validate the density on the host (device inputs are copied back).
+    std::vector<double> host;
+    const double* r = rho_init;
+    if (on_device) {
+        host.resize(N);
+        if ((e = hipMemcpyAsync(host.data(), rho_init, N * sizeof(double), hipMemcpyDeviceToHost, st)) ||
+            (e = hipStreamSynchronize(st)))
+            return hip_fail(e, "copy rho_init");
+        if ((rc = field_check_host(host.data(), N, true, "rho_init"))) return rc;
+    } else {
+        if ((rc = field_check_host(rho_init, N, true, "rho_init"))) return rc;
+        if ((e = hipMemcpyAsync(c->staging, rho_init, N * sizeof(double), hipMemcpyHostToDevice, st)))
+            return hip_fail(e, "copy rho_init");
+        r = c->staging;
+    }
+    a->have_forward = false;
+    a->tape_seg = -1;
+    c->p.G1 = G1;
+    c->p.G2 = G2;
+    c->coef = make_coef(c->p);
+    a->ap.G1 = G1;
+    a->ap.G2 = G2;
+    c->cur = 0;
+    c->t = 0;
+    if ((e = lbk::launch_init(c->p.storage, r, nullptr, nullptr, c->buf[0], c->g, c->coef, st)))
+        return hip_fail(e, "init kernel");
+    for (int32_t s = 0; s < a->nseg; ++s) {
+        if ((e = hipMemcpyAsync(a->ckpt + (size_t)s * align_up(a->ckpt_bytes), c->buf[c->cur],
+                                a->ckpt_bytes, hipMemcpyDeviceToDevice, st)))
+            return hip_fail(e, "checkpoint copy");
+        const int64_t t0 = (int64_t)s * a->every;
+        const int64_t n = a->T - t0 < a->every ? a->T - t0 : a->every;
+        // The last segment is taped on the way, so the backward pass
+        // starts without recomputing it.
+        if (s + 1 < a->nseg) {
+            if ((rc = lb_step(c, n))) return rc;
+        } else {
+            if ((rc = adj_tape_steps(a, n))) return rc;
+            a->tape_seg = s;
+        }
+    }
+    if ((e = lbk::adj_tape(c->p.storage, c->buf[c->cur], c->g, a->ap, a->tapeT, st)) ||
+        (e = lbk::adj_area(a->ap, a->tapeT, loss->eps, a->dir, a->partA, st)) ||
+        (e = lbk::adj_reduce(a->partA, a->blocks, 1, a->red, st)))
+        return hip_fail(e, "interface measure");
+    if ((rc = energy_row(c, lbk::MODE_ENERGY, c->buf[c->cur], c->buf[c->cur ^ 1], c->scalars))) return rc;
+    double row[6], A = 0.0;
+    if ((e = hipMemcpyAsync(row, c->scalars, sizeof row, hipMemcpyDeviceToHost, st)) ||
+        (e = hipMemcpyAsync(&A, a->red, sizeof A, hipMemcpyDeviceToHost, st)) ||
+        (e = hipStreamSynchronize(st)))
+        return hip_fail(e, "copy loss terms");
+    a->E = row[2] + row[3];
+    a->A = A;
+    a->E_target = loss->E_target;
+    a->beta = loss->beta;
+    a->eps = loss->eps;
+    const double d = a->E - a->E_target;
+    out[0] = d * d + a->beta * A;
+    out[1] = a->E;
+    out[2] = A;
+    out[3] = row[1];
+    if (!std::isfinite(out[0]) || !std::isfinite(out[3]))
+        return fail(LB_ERR_NONFINITE, "non-finite loss or mass at T = %lld", (long long)a->T);
+    a->have_forward = true;
+    return LB_OK;
+}
+
+int lb_adj_backward(lb_adj* a, double dG[2], double* drho, int on_device)
+{
+    int rc = check_adj(a);
+    if (rc) return rc;
+    if (!dG || !drho) return fail(LB_ERR_INVALID, "NULL argument");
+    if (!a->have_forward) return fail(LB_ERR_STATE, "lb_adj_backward needs a successful lb_adj_forward");
+    lb_ctx* c = a->fwd;
+    DeviceGuard dg(c->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+    const int64_t N = (int64_t)c->p.nx * c->p.ny;
+    const size_t es = a->ap.f64 ? 8 : 4;
+    const size_t entry = (size_t)4 * N * es;
+    hipStream_t st = c->stream;
+    const double two_dE = 2.0 * (a->E - a->E_target);
+    hipError_t e;
+    if ((e = lbk::adj_area(a->ap, a->tapeT, a->eps, a->dir, a->partA, st)) ||
+        (e = lbk::adj_seed(a->ap, a->tapeT, a->dir, two_dE, a->beta, a->lam[0], a->g[0], a->partE, st)) ||
+        (e = lbk::adj_zero(a->part, (int64_t)a->blocks * 2, st)))
+        return hip_fail(e, "adjoint seed");
+    int cur = 0;
+    for (int32_t s = a->nseg - 1; s >= 0; --s) {
+        const int64_t t0 = (int64_t)s * a->every;
+        const int64_t n = a->T - t0 < a->every ? a->T - t0 : a->every;
+        // Recompute the segment from its checkpoint, taping each state
+        // (unless the tape region still holds this segment).
+        if (a->tape_seg != s) {
+            a->tape_seg = -1;
+            if ((e = hipMemcpyAsync(c->buf[c->cur], a->ckpt + (size_t)s * align_up(a->ckpt_bytes),
+                                    a->ckpt_bytes, hipMemcpyDeviceToDevice, st)))
+                return hip_fail(e, "checkpoint restore");
+            c->t = t0;
+            if ((rc = adj_tape_steps(a, n))) return rc;
+            a->tape_seg = s;
+        }
+        for (int64_t j = n - 1; j >= 0; --j) {
+            if ((e = lbk::adj_step(a->ap, a->lam[cur], a->g[cur], a->tape + j * entry, a->lam[cur ^ 1],
+                                   a->g[cur ^ 1], a->gF, a->part, st)))
+                return hip_fail(e, "adjoint step");
+            cur ^= 1;
+        }
+    }
+    double* dst = on_device ? drho : a->drho;
+    if ((e = lbk::adj_rho_grad(a->ap, a->lam[cur], a->g[cur], dst, st)) ||
+        (e = lbk::adj_reduce(a->part, a->blocks, 2, a->red + 2, st)) ||
+        (e = lbk::adj_reduce(a->partE, a->blocks, 2, a->red + 4, st)))
+        return hip_fail(e, "adjoint reductions");
+    double r[4];
+    if ((e = hipMemcpyAsync(r, a->red + 2, sizeof r, hipMemcpyDeviceToHost, st)))
+        return hip_fail(e, "copy gradients");
+    if (!on_device && (e = hipMemcpyAsync(drho, a->drho, N * sizeof(double), hipMemcpyDeviceToHost, st)))
+        return hip_fail(e, "copy gradients");
+    if ((e = hipStreamSynchronize(st))) return hip_fail(e, "synchronise");
+    dG[0] = r[0] + two_dE * r[2];
+    dG[1] = r[1] + two_dE * r[3];
+    if (!std::isfinite(dG[0]) || !std::isfinite(dG[1]))
+        return fail(LB_ERR_NONFINITE, "non-finite coupling gradient");
+    return LB_OK;
+}
+
+int lb_adj_destroy(lb_adj* a)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!a || !g_adjs.count(a)) return fail(LB_ERR_STATE, "unknown or destroyed adjoint context");
+        g_adjs.erase(a);
+    }
+    const int rc = lb_destroy(a->fwd);
+    delete a;
+    return rc;
 }
 
 }  // extern "C"

@@ -15,7 +15,11 @@ enum Storage { ST_F64 = 0, ST_F32 = 1, ST_F16DEV = 2 };
 enum Mode {
     MODE_STEP = 0,         // stream + collide + store
     MODE_STEP_ENERGY = 1,  // the same, plus the energy/mass block partials
-    MODE_ENERGY = 2        // energy/mass block partials only, no store
+    MODE_ENERGY = 2,       // energy/mass block partials only, no store
+    MODE_STEP_TAPE = 3     // stream + collide + store, plus (rho, jx, jy, psi)
+                           // of every site's pre-collision state into a dense
+                           // [4][ny][nx] array of the arithmetic type, passed
+                           // in place of the partials (F64 and F32 only)
 };
 
 // Lattice geometry and launch shape.  Populations live in two buffers of
@@ -80,5 +84,36 @@ hipError_t launch_get_state(int storage, const void* src, void* dense,
                             const Geom& g, hipStream_t s);
 hipError_t launch_set_state(int storage, const void* dense, void* dst,
                             const Geom& g, hipStream_t s);
+
+// Adjoint kernels (lb_adjoint.hip).  Arithmetic is double when f64 != 0,
+// float otherwise; arrays are dense [component][ny][nx] of that type.
+struct AdjParams {
+    int32_t nx, ny;
+    int32_t f64;
+    double G1, G2, tau, sqrt_rho0, inv_rho0;
+};
+
+// Workgroups of every per-site adjoint kernel (one thread per site).
+int adj_blocks(int64_t sites);
+// tape[4][ny][nx] = (rho, jx, jy, psi) of the state held in a pitched
+// population buffer of the given storage (ST_F64 or ST_F32).
+hipError_t adj_tape(int storage, const void* buf, const Geom& g, const AdjParams& p, void* tape,
+                    hipStream_t s);
+// One adjoint step: (lam_next, g_next) at t+1 -> (lam, g) at t; gF[2][ny][nx]
+// is scratch; part[adj_blocks][2] accumulates dL/dG1, dL/dG2.
+hipError_t adj_step(const AdjParams& p, const void* lam_next, const void* g_next, const void* tape,
+                    void* lam, void* g, void* gF, double* part, hipStream_t s);
+// Interface measure of a tape entry: dir[2][ny][nx], part[adj_blocks] sums.
+hipError_t adj_area(const AdjParams& p, const void* tape, double eps, void* dir, double* part,
+                    hipStream_t s);
+// Adjoint at T of L = (E - E*)^2 + beta A; part[adj_blocks][2] receives the
+// workgroup sums of dE/dG1, dE/dG2.
+hipError_t adj_seed(const AdjParams& p, const void* tape, const void* dir, double two_dE, double beta,
+                    void* lam, void* g, double* part, hipStream_t s);
+// out[ny][nx] (double) = sum_i w_i (lam_i + g).
+hipError_t adj_rho_grad(const AdjParams& p, const void* lam, const void* g, double* out, hipStream_t s);
+// out[v] = sum_b part[b * nv + v] for v < nv, fixed order.
+hipError_t adj_reduce(const double* part, int blocks, int nv, double* out, hipStream_t s);
+hipError_t adj_zero(double* p, int64_t n, hipStream_t s);
 
 }  // namespace lbk

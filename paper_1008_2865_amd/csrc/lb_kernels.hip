@@ -252,8 +252,9 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
 {
     using S = typename P::S;
     using C = typename P::C;
-    constexpr bool kEnergy = MODE != MODE_STEP;
+    constexpr bool kEnergy = MODE == MODE_STEP_ENERGY || MODE == MODE_ENERGY;
     constexpr bool kCollide = MODE != MODE_ENERGY;
+    constexpr bool kTape = MODE == MODE_STEP_TAPE;
     constexpr int LW = NT + 4;
     constexpr int kWaves = NT / 64;
     constexpr int kHpw = 4 / kWaves;  // halo columns gathered per wave
@@ -387,6 +388,7 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
         __syncthreads();
 
         C q[RPI][9];
+        C tp[RPI][4];  // tape entry (MODE_STEP_TAPE)
         C anchor = (C)0;
 #pragma unroll
         for (int m = 0; m < RPI; ++m) {
@@ -457,6 +459,12 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
                 const C rho = density(R);
                 const C jx = (R[1] - R[3]) + ((R[5] - R[7]) + (R[8] - R[6]));
                 const C jy = (R[2] - R[4]) + ((R[5] - R[7]) + (R[6] - R[8]));
+                if (kTape) {
+                    tp[m][0] = rho;
+                    tp[m][1] = jx;
+                    tp[m][2] = jy;
+                    tp[m][3] = p;
+                }
                 const C inv = rcp_c(rho);
                 const C ux = fma_c(k.tau, Fx, jx) * inv;
                 const C uy = fma_c(k.tau, Fy, jy) * inv;
@@ -512,6 +520,12 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
                 const int yw = wrow(b + m);
                 const uint32_t rnd = P::kDev ? site_hash(xc, yw, k.step) : 0u;
                 store_site<P>(pd, yw * g.pitch + xc, q[m], o, rnd);
+                if (kTape) {
+                    C* tape = reinterpret_cast<C*>(partials);
+                    const int64_t N = (int64_t)nx * ny, si = (int64_t)yw * nx + xc;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) tape[v * N + si] = tp[m][v];
+                }
             }
         }
     };
@@ -723,7 +737,12 @@ hipError_t step_nt(int mode, const void* src, void* dst, const Geom& g,
         hipLaunchKernelGGL((k_step<P, NT, MODE_STEP, RPI>), grid, block, 0, s, a, b, g, k, partials);
     else if (mode == MODE_STEP_ENERGY)
         hipLaunchKernelGGL((k_step<P, NT, MODE_STEP_ENERGY, RPI>), grid, block, 0, s, a, b, g, k, partials);
-    else
+    else if (mode == MODE_STEP_TAPE) {
+        if constexpr (P::kDev)
+            return hipErrorInvalidValue;
+        else
+            hipLaunchKernelGGL((k_step<P, NT, MODE_STEP_TAPE, RPI>), grid, block, 0, s, a, b, g, k, partials);
+    } else
         hipLaunchKernelGGL((k_step<P, NT, MODE_ENERGY, RPI>), grid, block, 0, s, a, b, g, k, partials);
     return hipGetLastError();
 }

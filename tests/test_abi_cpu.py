@@ -149,3 +149,26 @@ def test_batch_rejects_mismatched_settings():
                 [B.make_params(64, 64, tile_x=64), B.make_params(4, 64, tile_x=64)]):
         assert B.lb_batch_workspace_bytes(bad) == 0
         assert P.lb_last_error()
+
+
+def test_adjoint_host_validation():
+    p = B.make_params(64, 48, storage=P.LB_F32)
+    nb = B.lb_adj_workspace_bytes(p, 300, 100)
+    # The forward workspace, three 9-plane checkpoints and a 100-entry tape
+    # of 4 values per site.
+    assert nb > P.lb_workspace_bytes(p) + (3 * 9 + 100 * 4) * 64 * 48 * 4
+    assert B.lb_adj_workspace_bytes(p, 600, 100) > nb         # more checkpoints
+    assert B.lb_adj_workspace_bytes(p, 0, 1) > 0               # T = 0 is valid
+    for bad in [(B.make_params(64, 48, storage=P.LB_F16DEV), 10, 5),
+                (p, -1, 5), (p, 10, 0), (B.make_params(4, 48), 10, 5)]:
+        assert B.lb_adj_workspace_bytes(*bad) == 0
+    for fn, args in [(B.lb_adj_backward, (np.zeros((48, 64)),)), (B.lb_adj_destroy, ()),
+                     (B.lb_adj_forward, (np.full((48, 64), 0.7), -5.0, 0.5, 0.0, 0.0, 1e-6))]:
+        with pytest.raises(B.LBError) as e:
+            fn(0x1234560, *args)
+        assert e.value.code == B.LB_ERR_STATE
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        with pytest.raises(B.LBError) as e:
+            B.lb_adj_init(p, 300, 100, 256, nb)
+        assert e.value.code == B.LB_ERR_HIP

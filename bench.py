@@ -97,10 +97,11 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=None)
     ap.add_argument("--copy-calib", action="store_true",
                     help="also run a device copy of one population buffer (counter calibration)")
-    ap.add_argument("--workload", default="single", choices=["single", "batch", "adjoint"],
+    ap.add_argument("--workload", default="single", choices=["single", "batch", "adjoint", "structure"],
                     help="single: one lattice (default, the headline workload); batch: the "
                          "96-lattice sweep of independent lattices; adjoint: gradients of the "
-                         "droplet functional at 512^2 (adjoint/forward time ratio)")
+                         "droplet functional at 512^2 (adjoint/forward time ratio); structure: "
+                         "the structure factor S(k), shell average and kbar at 512^2 and 2048^2")
     ap.add_argument("--checkpoint-every", type=int, default=100)
     args = ap.parse_args()
 
@@ -125,6 +126,8 @@ def main():
         return bench_batch(args)
     if args.workload == "adjoint":
         return bench_adjoint(args)
+    if args.workload == "structure":
+        return bench_structure(args)
     n, K, W, le = args.n, args.steps, args.warmup, args.log_every
     G1, G2 = inputs.couplings(args.r)
     rho0 = inputs.rho_noise(n, n, args.seed)
@@ -400,6 +403,73 @@ def bench_adjoint(args):
             "value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS (forward + gradient)",
             "cores": torch.get_num_threads(), "kind": "oracle",
             "sample": f"{n}x{n}, {steps} steps, FP64 autograd oracle, {dt:.1f} s wall"}
+    print(json.dumps(out), flush=True)
+
+
+def bench_structure(args):
+    """The structure factor of section IV (mean, row FFTs, transpose, column
+    FFTs with |.|^2 / N, shell averages, kbar) on seeded density fields of
+    512^2 and 2048^2, FP64; GPU time per evaluation from HIP events on the
+    library's stream, synchronous host copies of the shells included."""
+    import numpy as np
+    import torch
+
+    from paper_1008_2865_amd import binding as B
+    from paper_1008_2865_amd import inputs
+    from paper_1008_2865_amd.structure import StructureFactor
+
+    reps = 50
+    res = {}
+    for L in (512, 2048):
+        sk = StructureFactor(L)
+        rho = torch.tensor(inputs.rho_noise(L, L, args.seed, amp=0.2), device="cuda")
+        shell = np.empty(sk.nshell)
+        counts = np.empty(sk.nshell, np.int64)
+        for _ in range(3):
+            B.lb_sk_compute(sk.ctx, rho, shell, counts, on_device=True)
+        torch.cuda.synchronize()
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        a.record(sk.stream)
+        for _ in range(reps):
+            kbar = B.lb_sk_compute(sk.ctx, rho, shell, counts, on_device=True)
+        b.record(sk.stream)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) / reps
+        gpu = a.elapsed_time(b) / 1e3 / reps
+        # Bytes of the two-pass transform: rho in, row spectra out (8 + 16),
+        # transpose (16 + 16), column spectra in, |.|^2 out (16 + 8), shell
+        # pass (8 + 4 index bytes) per mode.
+        res[L] = {"us_per_eval": round(gpu * 1e6, 2), "wall_us_per_eval": round(wall * 1e6, 2),
+                  "effective_gbps": round(92 * L * L / gpu / 1e9, 1), "kbar": kbar}
+        log(f"bench: S(k) L={L}: {gpu * 1e6:.1f} us (GPU), {wall * 1e6:.1f} us (wall)")
+        sk.close()
+    out = {
+        "metric": "structure factor evaluations per second (S(k), shell average, kbar)",
+        "value": round(1.0 / (res[2048]["us_per_eval"] / 1e6), 1), "unit": "evaluations/s",
+        "n_gpus": 1, "steps": reps, "warmup": 3,
+        "ms_per_step": round(res[2048]["us_per_eval"] / 1e3, 6), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "structure factor of a seeded 2048x2048 density field "
+                               "(0.7 (1 + 0.2 U(-1, 1))), FP64 FFTs in LDS, 1449 shells; "
+                               "512x512 alongside"},
+        "sizes": {str(k): v for k, v in res.items()},
+    }
+    if args.cpu_seconds > 0 or args.cpu_steps:
+        from oracle import structure as OS
+
+        rho = inputs.rho_noise(2048, 2048, args.seed, amp=0.2)
+        t0 = time.perf_counter()
+        n = 0
+        while time.perf_counter() - t0 < min(args.cpu_seconds, 10.0) or n == 0:
+            Sn, _ = OS.shells(rho)
+            OS.kbar(Sn)
+            n += 1
+        dt = (time.perf_counter() - t0) / n
+        out["cpu_baseline"] = {"value": round(1.0 / dt, 3), "unit": "evaluations/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"2048x2048, {n} evaluations of the numpy oracle, {dt:.2f} s each"}
     print(json.dumps(out), flush=True)
 
 

@@ -267,6 +267,44 @@ int lb_adj_backward(lb_adj* a, double dG[2], double* drho, int on_device);
 /* Release the adjoint context (after synchronising its stream). */
 int lb_adj_destroy(lb_adj* a);
 
+/* ---------------------------------------------------------------------------
+ * Structure factor (the Fourier analysis of section IV) of a density field
+ * on an L x L periodic lattice, 5 <= L <= 2048:
+ *   S(k) = (1/N) |sum_x (rho(x) - mean rho) exp(i k.x)|^2,
+ *   k = (2 pi / L)(l, m), N = L^2;
+ *   S_n = mean of S(k) over the shell (n - 1/2) <= |k| L / (2 pi) < n + 1/2,
+ *         n = 0 .. nshell-1 (every mode lies in exactly one shell);
+ *   kbar = sum_n n S_n / sum_n S_n (eq. rad, k in units of 2 pi / L);
+ *   the droplet length scale is then R = L / (2 kbar) (k = 1 gives L/2).
+ * Computed in double precision by FFTs in LDS (a direct transform when L is
+ * not a power of two); every sum has a fixed order, so repeated calls give
+ * bit-identical results.  Workspace and stream rules are those of lb_init.
+ * ------------------------------------------------------------------------ */
+typedef struct lb_sk lb_sk;
+
+/* Number of shells of an L x L lattice (host only). */
+int lb_sk_shells(int32_t L, int32_t* nshell);
+
+/* Device workspace bytes for side L, or 0 if L is out of range. */
+size_t lb_sk_workspace_bytes(int32_t L);
+
+/* Create a structure-factor context for side L (builds the shell tables). */
+int lb_sk_init(lb_sk** out, int32_t L, void* workspace, size_t bytes,
+               void* hip_stream);
+
+/* Structure factor of rho (L*L doubles, row-major [y][x], device memory if
+ * on_device = 1, else host).  Writes, synchronously, up to cap shells:
+ * shell[n] = S_n and counts[n] = modes in shell n (host arrays; either may
+ * be NULL), *kbar (may be NULL) and, if spectrum is not NULL, the full S(k)
+ * as a device array of L*L doubles indexed [m][l] (l, m the FFT indices of
+ * x and y).  LB_ERR_NONFINITE if a shell value or kbar is not finite (kbar
+ * is undefined for a uniform field). */
+int lb_sk_compute(lb_sk* s, const double* rho, int on_device, double* shell,
+                  int64_t* counts, int32_t cap, double* kbar, double* spectrum);
+
+/* Release the context (after synchronising its stream). */
+int lb_sk_destroy(lb_sk* s);
+
 #ifdef __cplusplus
 }
 #endif

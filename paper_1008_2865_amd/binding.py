@@ -79,6 +79,11 @@ SIGNATURES = {
                                       ctypes.POINTER(lb_adj_loss), _vp]),
     "lb_adj_backward": (ctypes.c_int, [_vp, _vp, _vp, ctypes.c_int]),
     "lb_adj_destroy": (ctypes.c_int, [_vp]),
+    "lb_sk_shells": (ctypes.c_int, [ctypes.c_int32, _vp]),
+    "lb_sk_workspace_bytes": (ctypes.c_size_t, [ctypes.c_int32]),
+    "lb_sk_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
+    "lb_sk_compute": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int32, _vp, _vp]),
+    "lb_sk_destroy": (ctypes.c_int, [_vp]),
 }
 
 _lib = None
@@ -260,3 +265,32 @@ def lb_adj_backward(a, drho, on_device=False):
 
 def lb_adj_destroy(a):
     return _check(lib().lb_adj_destroy(a))
+
+
+def lb_sk_shells(L):
+    n = ctypes.c_int32()
+    _check(lib().lb_sk_shells(L, ctypes.byref(n)))
+    return n.value
+
+
+def lb_sk_workspace_bytes(L):
+    return lib().lb_sk_workspace_bytes(L)
+
+
+def lb_sk_init(L, workspace, nbytes, stream=0):
+    s = _vp()
+    _check(lib().lb_sk_init(ctypes.byref(s), L, _ptr(workspace), nbytes, stream or None))
+    return s.value
+
+
+def lb_sk_compute(s, rho, shell, counts, kbar_out=None, spectrum=None, on_device=False):
+    """Fills shell / counts (numpy float64 / int64 arrays or None); returns kbar."""
+    cap = len(shell) if shell is not None else (len(counts) if counts is not None else 0)
+    kb = ctypes.c_double()
+    _check(lib().lb_sk_compute(s, _ptr(rho), int(bool(on_device)), _ptr(shell), _ptr(counts),
+                               cap, ctypes.byref(kb), _ptr(spectrum)))
+    return kb.value
+
+
+def lb_sk_destroy(s):
+    return _check(lib().lb_sk_destroy(s))

@@ -9,6 +9,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -1221,6 +1222,216 @@ int lb_adj_destroy(lb_adj* a)
     const int rc = lb_destroy(a->fwd);
     delete a;
     return rc;
+}
+
+
+// ---------------------------------------------------------------------------
+// Structure factor of a density field.
+// ---------------------------------------------------------------------------
+struct lb_sk {
+    lbk::SkPlan plan;
+    std::vector<int64_t> counts;  // modes per shell
+    double* rho;                  // device staging of host input, L*L doubles
+    int device;
+    hipStream_t stream;
+};
+
+namespace {
+
+std::set<lb_sk*> g_sks;
+
+int check_sk(lb_sk* s)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!s || !g_sks.count(s)) return fail(LB_ERR_STATE, "unknown or destroyed structure-factor context");
+    return LB_OK;
+}
+
+// Shell of a mode with l^2 + m^2 = q: the n with (2n-1)^2 <= 4q < (2n+1)^2
+// (n - 1/2 <= sqrt(q) < n + 1/2), in integer arithmetic.
+int64_t shell_of(int64_t q)
+{
+    int64_t n = (int64_t)std::floor(std::sqrt((double)q) + 0.5);
+    while ((2 * n + 1) * (2 * n + 1) <= 4 * q) ++n;
+    while (n > 0 && (2 * n - 1) * (2 * n - 1) > 4 * q) --n;
+    return n;
+}
+
+int sk_check_L(int32_t L)
+{
+    if (L < 5 || L > lbk::kSkMaxL)
+        return fail(LB_ERR_INVALID, "L must be in [5, %d] (got %d)", lbk::kSkMaxL, L);
+    return LB_OK;
+}
+
+struct SkLayout {
+    size_t tw, part, mean, z, zt, spec, idx, off, shell, kbar, rho, total;
+    int32_t nshell, sum_blocks;
+};
+
+SkLayout sk_layout(int32_t L)
+{
+    SkLayout S;
+    const int64_t N = (int64_t)L * L;
+    const int64_t h = L / 2;  // largest |l| of an L-point transform
+    S.nshell = (int32_t)shell_of(2 * h * h) + 1;
+    S.sum_blocks = (int32_t)std::min<int64_t>(1024, (N + 255) / 256);
+    size_t off = 0;
+    S.tw = off; off += align_up((size_t)L * 2 * sizeof(double));
+    S.part = off; off += align_up((size_t)S.sum_blocks * sizeof(double));
+    S.mean = off; off += align_up(sizeof(double));
+    S.z = off; off += align_up((size_t)N * 2 * sizeof(double));
+    S.zt = off; off += align_up((size_t)N * 2 * sizeof(double));
+    S.spec = off; off += align_up((size_t)N * sizeof(double));
+    S.idx = off; off += align_up((size_t)N * sizeof(int32_t));
+    S.off = off; off += align_up((size_t)(S.nshell + 1) * sizeof(int32_t));
+    S.shell = off; off += align_up((size_t)S.nshell * sizeof(double));
+    S.kbar = off; off += align_up(2 * sizeof(double));
+    S.rho = off; off += align_up((size_t)N * sizeof(double));
+    S.total = off;
+    return S;
+}
+
+}  // namespace
+
+int lb_sk_shells(int32_t L, int32_t* nshell)
+{
+    int rc = sk_check_L(L);
+    if (rc) return rc;
+    if (!nshell) return fail(LB_ERR_INVALID, "nshell is NULL");
+    *nshell = sk_layout(L).nshell;
+    return LB_OK;
+}
+
+size_t lb_sk_workspace_bytes(int32_t L)
+{
+    return sk_check_L(L) ? 0 : sk_layout(L).total;
+}
+
+int lb_sk_init(lb_sk** out, int32_t L, void* workspace, size_t bytes, void* hip_stream)
+{
+    if (!out) return fail(LB_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int rc = sk_check_L(L);
+    if (rc) return rc;
+    const SkLayout S = sk_layout(L);
+    if (!workspace) return fail(LB_ERR_INVALID, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(workspace) % kAlign)
+        return fail(LB_ERR_INVALID, "workspace must be %zu-byte aligned", kAlign);
+    if (bytes < S.total) return fail(LB_ERR_INVALID, "workspace too small: %zu < %zu bytes", bytes, S.total);
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) return fail(LB_ERR_HIP, "no HIP device available");
+    int dev = 0;
+    if ((e = hipGetDevice(&dev))) return hip_fail(e, "hipGetDevice");
+
+    // Modes grouped by shell, each group in increasing index order (index
+    // l * L + m of the [l][m] spectrum; l, m signed as in an FFT).
+    const int64_t N = (int64_t)L * L;
+    std::vector<int32_t> shell_n(N), off(S.nshell + 1, 0), idx(N);
+    for (int32_t l = 0; l < L; ++l) {
+        const int64_t ls = l <= (L - 1) / 2 ? l : l - L;
+        for (int32_t m = 0; m < L; ++m) {
+            const int64_t ms = m <= (L - 1) / 2 ? m : m - L;
+            const int32_t n = (int32_t)shell_of(ls * ls + ms * ms);
+            shell_n[(int64_t)l * L + m] = n;
+            ++off[n + 1];
+        }
+    }
+    for (int32_t n = 0; n < S.nshell; ++n) off[n + 1] += off[n];
+    std::vector<int32_t> pos(off.begin(), off.end() - 1);
+    for (int64_t i = 0; i < N; ++i) idx[pos[shell_n[i]]++] = (int32_t)i;
+
+    char* ws = static_cast<char*>(workspace);
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    lb_sk* s = new lb_sk();
+    lbk::SkPlan& p = s->plan;
+    p.L = L;
+    p.logL = 0;
+    if ((L & (L - 1)) == 0)
+        while ((1 << p.logL) < L) ++p.logL;
+    p.nshell = S.nshell;
+    p.sum_blocks = S.sum_blocks;
+    p.tw = reinterpret_cast<double2*>(ws + S.tw);
+    p.part = reinterpret_cast<double*>(ws + S.part);
+    p.mean = reinterpret_cast<double*>(ws + S.mean);
+    p.z = reinterpret_cast<double2*>(ws + S.z);
+    p.zt = reinterpret_cast<double2*>(ws + S.zt);
+    p.spec_t = reinterpret_cast<double*>(ws + S.spec);
+    p.idx = reinterpret_cast<const int32_t*>(ws + S.idx);
+    p.off = reinterpret_cast<const int32_t*>(ws + S.off);
+    p.shell = reinterpret_cast<double*>(ws + S.shell);
+    p.kbar = reinterpret_cast<double*>(ws + S.kbar);
+    s->rho = reinterpret_cast<double*>(ws + S.rho);
+    s->device = dev;
+    s->stream = st;
+    s->counts.resize(S.nshell);
+    for (int32_t n = 0; n < S.nshell; ++n) s->counts[n] = off[n + 1] - off[n];
+    if ((e = hipMemcpyAsync(ws + S.idx, idx.data(), N * sizeof(int32_t), hipMemcpyHostToDevice, st)) ||
+        (e = hipMemcpyAsync(ws + S.off, off.data(), off.size() * sizeof(int32_t), hipMemcpyHostToDevice, st)) ||
+        (e = lbk::sk_twiddles(p, st)) || (e = hipStreamSynchronize(st))) {
+        delete s;
+        return hip_fail(e, "copy shell tables");
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        g_sks.insert(s);
+    }
+    *out = s;
+    return LB_OK;
+}
+
+int lb_sk_compute(lb_sk* s, const double* rho, int on_device, double* shell, int64_t* counts,
+                  int32_t cap, double* kbar, double* spectrum)
+{
+    int rc = check_sk(s);
+    if (rc) return rc;
+    if (!rho) return fail(LB_ERR_INVALID, "rho is NULL");
+    if (cap < 0 || (cap > 0 && !shell && !counts)) return fail(LB_ERR_INVALID, "bad shell outputs");
+    const lbk::SkPlan& p = s->plan;
+    const int64_t N = (int64_t)p.L * p.L;
+    DeviceGuard dg(s->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+    hipError_t e;
+    const double* r = rho;
+    if (!on_device) {
+        if ((rc = field_check_host(rho, N, false, "rho"))) return rc;
+        if ((e = hipMemcpyAsync(s->rho, rho, N * sizeof(double), hipMemcpyHostToDevice, s->stream)))
+            return hip_fail(e, "copy rho");
+        r = s->rho;
+    }
+    if ((e = lbk::sk_compute(p, r, spectrum, s->stream))) return hip_fail(e, "structure-factor kernels");
+    const int32_t n = cap < p.nshell ? cap : p.nshell;
+    std::vector<double> sh(p.nshell);
+    double kb[2] = {0.0, 0.0};
+    if ((e = hipMemcpyAsync(sh.data(), p.shell, p.nshell * sizeof(double), hipMemcpyDeviceToHost, s->stream)) ||
+        (e = hipMemcpyAsync(kb, p.kbar, sizeof kb, hipMemcpyDeviceToHost, s->stream)) ||
+        (e = hipStreamSynchronize(s->stream)))
+        return hip_fail(e, "copy shells");
+    for (int32_t i = 0; i < n; ++i) {
+        if (shell) shell[i] = sh[i];
+        if (counts) counts[i] = s->counts[i];
+    }
+    if (kbar) *kbar = kb[0];
+    for (double v : sh)
+        if (!std::isfinite(v)) return fail(LB_ERR_NONFINITE, "non-finite structure factor");
+    if (kbar && !std::isfinite(kb[0]))
+        return fail(LB_ERR_NONFINITE, "kbar is not finite (uniform field: every S_n is 0)");
+    return LB_OK;
+}
+
+int lb_sk_destroy(lb_sk* s)
+{
+    {
+        std::lock_guard<std::mutex> lk(g_mu);
+        if (!s || !g_sks.count(s)) return fail(LB_ERR_STATE, "unknown or destroyed structure-factor context");
+        g_sks.erase(s);
+    }
+    DeviceGuard dg(s->device);
+    hipError_t e = hipStreamSynchronize(s->stream);
+    delete s;
+    if (e) return hip_fail(e, "synchronise");
+    return LB_OK;
 }
 
 }  // extern "C"

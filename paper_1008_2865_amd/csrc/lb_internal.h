@@ -116,4 +116,28 @@ hipError_t adj_rho_grad(const AdjParams& p, const void* lam, const void* g, doub
 hipError_t adj_reduce(const double* part, int blocks, int nv, double* out, hipStream_t s);
 hipError_t adj_zero(double* p, int64_t n, hipStream_t s);
 
+// Structure factor (lb_structure.hip) of an L x L density field, L <= kSkMaxL.
+constexpr int kSkMaxL = 2048;
+struct SkPlan {
+    int32_t L;
+    int32_t logL;        // log2 L if L is a power of two, else 0 (direct DFT)
+    int32_t nshell;      // shells 0 .. nshell-1
+    int32_t sum_blocks;  // workgroups of the mean reduction
+    double2* tw;         // L twiddles exp(-2 pi i k / L)
+    double* part;        // sum_blocks partial sums
+    double* mean;        // 1
+    double2* z;          // L*L: row transforms, [y][l]
+    double2* zt;         // L*L: their transpose, [l][y]
+    double* spec_t;      // L*L: S at (l, m), stored [l][m]
+    const int32_t* idx;  // L*L: indices into spec_t, grouped by shell
+    const int32_t* off;  // nshell + 1: shell n is idx[off[n] .. off[n+1])
+    double* shell;       // nshell shell averages
+    double* kbar;        // 2: {kbar, sum_n S_n}
+};
+// Runs every pass on rho (device, L*L doubles); spectrum (device, [m][l])
+// may be NULL.
+hipError_t sk_compute(const SkPlan& p, const double* rho, double* spectrum, hipStream_t s);
+// Fills p.tw (once per plan).
+hipError_t sk_twiddles(const SkPlan& p, hipStream_t s);
+
 }  // namespace lbk

@@ -88,6 +88,18 @@ class LBSim:
         B.lb_pseudo_energy(self.ctx, out)
         return out
 
+    def structure_factor(self, spectrum=False):
+        """(S_n, counts, kbar, R) of the density at t (square lattices; see
+        structure.StructureFactor)."""
+        if getattr(self, "_sk", None) is None:
+            from .structure import StructureFactor
+
+            if self.nx != self.ny:
+                raise ValueError("the structure factor is defined for square lattices")
+            self._sk = StructureFactor(self.nx)
+        rho = self.moments(device=True)[0]
+        return self._sk(rho, spectrum=spectrum)
+
     def trace(self):
         out = np.empty((max(self.trace_cap, 1), 6), np.float64)
         n = B.lb_trace(self.ctx, out, self.trace_cap)
@@ -108,6 +120,9 @@ class LBSim:
         B.lb_set_state(self.ctx, f, t, on_device=False)
 
     def close(self):
+        if getattr(self, "_sk", None) is not None:
+            self._sk.close()
+            self._sk = None
         if getattr(self, "ctx", None):
             B.lb_destroy(self.ctx)
             self.ctx = None

@@ -172,3 +172,24 @@ def test_adjoint_host_validation():
         with pytest.raises(B.LBError) as e:
             B.lb_adj_init(p, 300, 100, 256, nb)
         assert e.value.code == B.LB_ERR_HIP
+
+
+def test_structure_factor_host_side():
+    from oracle import structure as OS
+
+    for L in (5, 8, 37, 64, 512, 2048):
+        assert B.lb_sk_shells(L) == int(OS.shell_index(L).max()) + 1
+        assert B.lb_sk_workspace_bytes(L) > 40 * L * L
+    for L in (4, 2049, 0, -3):
+        assert B.lb_sk_workspace_bytes(L) == 0
+        with pytest.raises(B.LBError) as e:
+            B.lb_sk_shells(L)
+        assert e.value.code == B.LB_ERR_INVALID
+    with pytest.raises(B.LBError) as e:
+        B.lb_sk_compute(0x1234560, np.zeros((8, 8)), np.zeros(4), None)
+    assert e.value.code == B.LB_ERR_STATE
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        with pytest.raises(B.LBError) as e:
+            B.lb_sk_init(64, 256, B.lb_sk_workspace_bytes(64))
+        assert e.value.code == B.LB_ERR_HIP

@@ -198,7 +198,7 @@ struct lb_batch {
     int32_t* tile_lattice;     // device
     double* partials;          // device, 4 per tile
     int tiles;
-    int storage, tile_x, rows_per_iter;
+    int storage, tile_x, rows_per_iter, min_tile_y;
     int device;
     hipStream_t stream;
     int parity;
@@ -656,7 +656,7 @@ int batch_layout(const lb_params* ps, int32_t count, BatchLayout* L)
 
 hipError_t batch_launch(lb_batch* b, int mode, int parity)
 {
-    return lbk::launch_step_batch(b->storage, mode, b->tile_x, b->rows_per_iter, b->desc,
+    return lbk::launch_step_batch(b->storage, mode, b->tile_x, b->rows_per_iter, b->min_tile_y, b->desc,
                                   b->tile_lattice, b->tiles, parity, (uint32_t)b->t, b->partials,
                                   b->stream);
 }
@@ -786,6 +786,8 @@ int lb_batch_init(lb_batch** out, const lb_params* ps, int32_t count, void* work
     b->tiles = L.tiles;
     b->storage = ps[0].storage;
     b->tile_x = c0->g.tile_x;
+    b->min_tile_y = c0->g.tile_y;
+    for (lb_ctx* m : b->members) b->min_tile_y = std::min(b->min_tile_y, m->g.tile_y);
     b->rows_per_iter = c0->g.rows_per_iter;
     b->device = c0->device;
     b->parity = 0;

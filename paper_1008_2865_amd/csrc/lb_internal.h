@@ -69,7 +69,7 @@ hipError_t launch_step(int storage, int mode, const void* src, void* dst,
                        hipStream_t s);
 hipError_t launch_final(const double* partials, int blocks, double t,
                         double half_A1, double* out_row, hipStream_t s);
-hipError_t launch_step_batch(int storage, int mode, int tile_x, int rows_per_iter,
+hipError_t launch_step_batch(int storage, int mode, int tile_x, int rows_per_iter, int min_tile_y,
                              const BatchLattice* desc, const int32_t* tile_lattice, int tiles,
                              int parity, uint32_t step, double* partials, hipStream_t s);
 hipError_t launch_final_batch(const BatchLattice* desc, int count, const double* partials,

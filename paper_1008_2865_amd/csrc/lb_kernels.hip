@@ -242,9 +242,23 @@ static_assert(((kCxPack >> 0) & 3u) == 1u && ((kCxPack >> 6) & 3u) == 0u &&
 template <int J>
 using Ic = std::integral_constant<int, J>;
 
+// Lookahead of the row walk: the loads of a row are issued LEAD
+// iterations before its psi is staged.  LEAD = 2 keeps two rows of loads in
+// flight per wave (about 10 more registers in single precision, still 4
+// waves per SIMD); its longer prologue only pays off on tall tiles.
+constexpr int kLead2MinRows = 16;
+
+// Plain steps of single-precision arithmetic with one row per stage have a
+// LEAD = 2 variant.
+template <class P, int RPI>
+constexpr bool lead2_variant()
+{
+    return sizeof(typename P::C) == 4 && RPI == 1;
+}
+
 // One launch = one time step for a tile of NT columns (one lane each) by
 // tile_y rows, walked RPI rows at a time.
-template <class P, int NT, int MODE, int RPI>
+template <class P, int NT, int MODE, int RPI, int LEAD>
 __device__ __forceinline__ void
 step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
           const Geom& g, const CoefT<typename P::C>& k, double* __restrict__ partials,
@@ -263,9 +277,10 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
     // updated, the 2 rows after them (psi staged) and RPI lead rows whose
     // loads are in flight.
     constexpr int RS = 4 + 2 * RPI;
-    constexpr int NB = 2 + 2 * RPI;
+    constexpr int NB = 2 + RPI * (1 + LEAD);
     constexpr int U = NB / RPI;
     static_assert(NB % RPI == 0, "buffer rotation must be a whole number of iterations");
+    static_assert(U <= 6, "the walk loop is unrolled at most 6 times");
     __shared__ C ring[RS][LW];
 
     const int tid = threadIdx.x;
@@ -336,17 +351,20 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
         if (lane < kHpw) ring[slot][mlds] = ps;
     };
 
-    // Walk row r lives in buffer r % NB.  Each loop iteration advances RPI
-    // rows and the loop body is unrolled U = NB / RPI times, so every
+    // Walk row r lives in buffer r % NB (its halo value in Hh[r % NB]).
+    // Each loop iteration advances RPI rows and the loop body is unrolled
+    // U = NB / RPI times, so every
     // buffer index below is a compile-time constant: the rotation is a
     // renaming, never a register copy (a copy of a register whose load may
     // still be outstanding would force a wait on the memory counter, which
     // on this target also counts the stores just issued).
     C Bf[NB][9] = {};
+    C Hh[NB] = {};
 
-    // Prologue: psi of walk rows -2 .. RPI+1 into ring slots 0 .. RPI+3 and
-    // the populations of rows 0 .. RPI+1 into Bf[0 .. RPI+1].  All rows are
-    // requested before any is used, so the prologue costs one latency.
+    // Prologue: psi of walk rows -2 .. RPI+1 into ring slots 0 .. RPI+3, the
+    // populations of rows 0 .. RPI+1 into Bf[0 .. RPI+1], and the loads of
+    // the first LEAD-1 stages of lead rows.  All rows are requested before
+    // any is used, so the prologue costs one latency.
     {
         C T0[9], T1[9], hv[RPI + 4];
         pull<P>(pl, g, xc, xcm, xcp, wrow(-2), o, T0);
@@ -355,6 +373,12 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
         for (int r = 0; r < RPI + 2; ++r) pull<P>(pl, g, xc, xcm, xcp, wrow(r), o, Bf[r]);
 #pragma unroll
         for (int r = -2; r < RPI + 2; ++r) hv[r + 2] = halo_load(wrow(r));
+#pragma unroll
+        for (int r = RPI + 2; r < 2 + RPI * LEAD; ++r) {
+            const int yl = r < nrows + 2 ? wrow(r) : wrow(0);
+            pull<P>(pl, g, xc, xcm, xcp, yl, o, Bf[r % NB]);
+            Hh[r % NB] = halo_load(yl);
+        }
         ring[0][tid + 2] = psi_of(density(T0), k);
         ring[1][tid + 2] = psi_of(density(T1), k);
 #pragma unroll
@@ -366,24 +390,24 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
     double aM = 0.0, aEs = 0.0, aEm = 0.0, aS2 = 0.0;
 
     // Software pipeline, per iteration (rows b .. b+RPI-1 along the walk):
-    //   issue the loads of the lead rows b+RPI+2 .. b+2RPI+1 | barrier |
-    //   force + collision of rows b .. b+RPI-1 | psi of the lead rows into
-    //   the ring slots of rows b-RPI-2 .. b-3 | stores.
-    // The loads overlap the barrier and the arithmetic; the stores overlap
-    // the next iteration's barrier and arithmetic.  The overwritten slots
-    // were last read in the previous iteration, before this barrier.  Lead
-    // rows past the end of the walk re-read row b instead (an L2 hit), so
-    // no load is conditional.
+    //   issue the loads of the rows LEAD stages ahead, b+2+RPI*LEAD .. |
+    //   barrier | force + collision of rows b .. b+RPI-1 | psi of rows
+    //   b+RPI+2 .. b+2RPI+1 (loaded LEAD-1 iterations ago) into the ring
+    //   slots of rows b-RPI-2 .. b-3 | stores.
+    // The loads overlap LEAD barriers and rounds of arithmetic; the stores
+    // overlap the next iteration's barrier and arithmetic.  The overwritten
+    // slots were last read in the previous iteration, before this barrier.
+    // Lead rows past the end of the walk re-read row b instead (an L2 hit),
+    // so no load is conditional.
     auto group = [&](auto Jc, int it, int s0) {
         constexpr int J = decltype(Jc)::value;
         const int b = it * RPI;
-        C hvl[RPI];
 #pragma unroll
         for (int m = 0; m < RPI; ++m) {
-            const int r = b + RPI + 2 + m;
+            const int r = b + 2 + RPI * LEAD + m;
             const int yl = r < nrows + 2 ? wrow(r) : wrow(b);
-            pull<P>(pl, g, xc, xcm, xcp, yl, o, Bf[(J * RPI + RPI + 2 + m) % NB]);
-            hvl[m] = halo_load(yl);
+            pull<P>(pl, g, xc, xcm, xcp, yl, o, Bf[(J * RPI + 2 + RPI * LEAD + m) % NB]);
+            Hh[(J * RPI + 2 + RPI * LEAD + m) % NB] = halo_load(yl);
         }
         __syncthreads();
 
@@ -503,13 +527,14 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
 #pragma unroll
         for (int m = 0; m < RPI; ++m) {
             C(&NF)[9] = Bf[(J * RPI + RPI + 2 + m) % NB];
+            C& HF = Hh[(J * RPI + RPI + 2 + m) % NB];
 #pragma unroll
             for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(NF[i]) : "v"(anchor));
-            asm volatile("" : "+v"(hvl[m]) : "v"(anchor));
+            asm volatile("" : "+v"(HF) : "v"(anchor));
             int sl = s0 + RPI + 4 + m;
             sl = sl >= RS ? sl - RS : sl;
             ring[sl][tid + 2] = psi_of(density(NF), k);
-            halo_psi(hvl[m], sl);
+            halo_psi(HF, sl);
         }
         __builtin_amdgcn_sched_barrier(0);
 
@@ -543,8 +568,18 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
         group(Ic<2 % U>{}, it, s0);
         s0 = step_slot(s0);
         if (++it * RPI >= nrows) break;
-        if constexpr (U == 4) {
-            group(Ic<3>{}, it, s0);
+        if constexpr (U >= 4) {
+            group(Ic<3 % U>{}, it, s0);
+            s0 = step_slot(s0);
+            if (++it * RPI >= nrows) break;
+        }
+        if constexpr (U >= 5) {
+            group(Ic<4 % U>{}, it, s0);
+            s0 = step_slot(s0);
+            if (++it * RPI >= nrows) break;
+        }
+        if constexpr (U >= 6) {
+            group(Ic<5 % U>{}, it, s0);
             s0 = step_slot(s0);
             if (++it * RPI >= nrows) break;
         }
@@ -569,12 +604,12 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
 
 // One launch = one time step of one lattice: workgroup b updates logical
 // tile xcd_remap(b).
-template <class P, int NT, int MODE, int RPI>
+template <class P, int NT, int MODE, int RPI, int LEAD>
 __global__ void __launch_bounds__(NT)
 k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
        Geom g, CoefT<typename P::C> k, double* __restrict__ partials)
 {
-    step_tile<P, NT, MODE, RPI>(src, dst, g, k, partials, xcd_remap(blockIdx.x, gridDim.x));
+    step_tile<P, NT, MODE, RPI, LEAD>(src, dst, g, k, partials, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // One launch = one time step of a batch of independent lattices.  The
@@ -583,7 +618,7 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
 // geometry, coefficients and buffers sit in desc.  Every lattice's tile is
 // processed exactly as the single-lattice kernel processes it, so fields
 // are bit-identical to single-lattice runs with the same tile shape.
-template <class P, int NT, int MODE, int RPI>
+template <class P, int NT, int MODE, int RPI, int LEAD>
 __global__ void __launch_bounds__(NT)
 k_step_batch(const BatchLattice* __restrict__ desc, const int32_t* __restrict__ tile_lattice,
              int parity, uint32_t step, double* __restrict__ partials)
@@ -594,7 +629,7 @@ k_step_batch(const BatchLattice* __restrict__ desc, const int32_t* __restrict__ 
     const BatchLattice& d = desc[lat];
     CoefT<typename P::C> k = convert<typename P::C>(d.coef);
     k.step = step;
-    step_tile<P, NT, MODE, RPI>(static_cast<const S*>(d.buf[parity]),
+    step_tile<P, NT, MODE, RPI, LEAD>(static_cast<const S*>(d.buf[parity]),
                                 static_cast<S*>(d.buf[parity ^ 1]), d.geom, k,
                                 partials + (int64_t)d.tile_begin * 4, gl - d.tile_begin);
 }
@@ -733,17 +768,23 @@ hipError_t step_nt(int mode, const void* src, void* dst, const Geom& g,
     const dim3 grid(g.blocks), block(NT);
     const S* a = static_cast<const S*>(src);
     S* b = static_cast<S*>(dst);
-    if (mode == MODE_STEP)
-        hipLaunchKernelGGL((k_step<P, NT, MODE_STEP, RPI>), grid, block, 0, s, a, b, g, k, partials);
-    else if (mode == MODE_STEP_ENERGY)
-        hipLaunchKernelGGL((k_step<P, NT, MODE_STEP_ENERGY, RPI>), grid, block, 0, s, a, b, g, k, partials);
+    if (mode == MODE_STEP) {
+        if constexpr (lead2_variant<P, RPI>()) {
+            if (g.tile_y >= kLead2MinRows) {
+                hipLaunchKernelGGL((k_step<P, NT, MODE_STEP, RPI, 2>), grid, block, 0, s, a, b, g, k, partials);
+                return hipGetLastError();
+            }
+        }
+        hipLaunchKernelGGL((k_step<P, NT, MODE_STEP, RPI, 1>), grid, block, 0, s, a, b, g, k, partials);
+    } else if (mode == MODE_STEP_ENERGY)
+        hipLaunchKernelGGL((k_step<P, NT, MODE_STEP_ENERGY, RPI, 1>), grid, block, 0, s, a, b, g, k, partials);
     else if (mode == MODE_STEP_TAPE) {
         if constexpr (P::kDev)
             return hipErrorInvalidValue;
         else
-            hipLaunchKernelGGL((k_step<P, NT, MODE_STEP_TAPE, RPI>), grid, block, 0, s, a, b, g, k, partials);
+            hipLaunchKernelGGL((k_step<P, NT, MODE_STEP_TAPE, RPI, 1>), grid, block, 0, s, a, b, g, k, partials);
     } else
-        hipLaunchKernelGGL((k_step<P, NT, MODE_ENERGY, RPI>), grid, block, 0, s, a, b, g, k, partials);
+        hipLaunchKernelGGL((k_step<P, NT, MODE_ENERGY, RPI, 1>), grid, block, 0, s, a, b, g, k, partials);
     return hipGetLastError();
 }
 
@@ -774,20 +815,28 @@ struct BatchLaunch {
     int parity;
     uint32_t step;
     double* partials;
+    int min_tile_y;  // smallest tile_y of the batch's lattices
 };
 
 template <class P, int NT, int RPI>
 hipError_t batch_nt(int mode, const BatchLaunch& a, hipStream_t s)
 {
     const dim3 grid(a.tiles), block(NT);
-    if (mode == MODE_STEP)
-        hipLaunchKernelGGL((k_step_batch<P, NT, MODE_STEP, RPI>), grid, block, 0, s, a.desc,
+    if (mode == MODE_STEP) {
+        if constexpr (lead2_variant<P, RPI>()) {
+            if (a.min_tile_y >= kLead2MinRows) {
+                hipLaunchKernelGGL((k_step_batch<P, NT, MODE_STEP, RPI, 2>), grid, block, 0, s, a.desc,
+                                   a.tile_lattice, a.parity, a.step, a.partials);
+                return hipGetLastError();
+            }
+        }
+        hipLaunchKernelGGL((k_step_batch<P, NT, MODE_STEP, RPI, 1>), grid, block, 0, s, a.desc,
                            a.tile_lattice, a.parity, a.step, a.partials);
-    else if (mode == MODE_STEP_ENERGY)
-        hipLaunchKernelGGL((k_step_batch<P, NT, MODE_STEP_ENERGY, RPI>), grid, block, 0, s, a.desc,
+    } else if (mode == MODE_STEP_ENERGY)
+        hipLaunchKernelGGL((k_step_batch<P, NT, MODE_STEP_ENERGY, RPI, 1>), grid, block, 0, s, a.desc,
                            a.tile_lattice, a.parity, a.step, a.partials);
     else
-        hipLaunchKernelGGL((k_step_batch<P, NT, MODE_ENERGY, RPI>), grid, block, 0, s, a.desc,
+        hipLaunchKernelGGL((k_step_batch<P, NT, MODE_ENERGY, RPI, 1>), grid, block, 0, s, a.desc,
                            a.tile_lattice, a.parity, a.step, a.partials);
     return hipGetLastError();
 }
@@ -806,11 +855,11 @@ hipError_t batch_p(int mode, int tile_x, int rpi, const BatchLaunch& a, hipStrea
 
 }  // namespace
 
-hipError_t launch_step_batch(int storage, int mode, int tile_x, int rows_per_iter,
+hipError_t launch_step_batch(int storage, int mode, int tile_x, int rows_per_iter, int min_tile_y,
                              const BatchLattice* desc, const int32_t* tile_lattice, int tiles,
                              int parity, uint32_t step, double* partials, hipStream_t s)
 {
-    const BatchLaunch a{desc, tile_lattice, tiles, parity, step, partials};
+    const BatchLaunch a{desc, tile_lattice, tiles, parity, step, partials, min_tile_y};
     switch (storage) {
     case ST_F64: return batch_p<PF64>(mode, tile_x, rows_per_iter, a, s);
     case ST_F32: return batch_p<PF32>(mode, tile_x, rows_per_iter, a, s);

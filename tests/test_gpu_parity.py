@@ -95,17 +95,22 @@ def test_f64_populations_match_oracle(nx, ny, tile_x, tile_y, tile_rows):
     sim.close()
 
 
-def test_fields_bit_identical_across_launch_shapes():
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_fields_bit_identical_across_launch_shapes(storage):
+    # Tiles of 16 rows and more take the two-row lookahead variant of the
+    # plain step, shorter ones the one-row variant; both, and every tile
+    # shape, must give the same bits (ragged last tiles included).
     G1, G2 = R01
     rho0 = inputs.rho_noise(300, 90, 4)
     states = []
     for tx, ty, tr in [(64, 1, 1), (64, 16, 1), (128, 7, 1), (256, 64, 1), (256, 90, 1),
                        (64, 1, 2), (128, 7, 2), (256, 32, 2), (256, 90, 2)]:
-        sim = gpu_run(rho0, 60, G1, G2, storage="f32", tile_x=tx, tile_y=ty, tile_rows=tr)
+        sim = gpu_run(rho0, 60, G1, G2, storage=storage, tile_x=tx, tile_y=ty, tile_rows=tr)
         states.append(sim.get_state())
         sim.close()
+    word = np.uint32 if storage == "f32" else np.uint16
     for s in states[1:]:
-        assert np.array_equal(s.view(np.uint32), states[0].view(np.uint32))
+        assert np.array_equal(s.view(word), states[0].view(word))
 
 
 def test_velocity_and_energy_match_oracle():

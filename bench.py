@@ -174,9 +174,10 @@ def main():
     step_s = sum(a.elapsed_time(b) for a, b, _ in pairs) / 1e3
     launches = sum(c for _, _, c in pairs)
     trace = sim.trace()
+    last_e = f"{trace[-1, 2] + trace[-1, 3]:.6g}" if len(trace) else "n/a"
     log(f"bench: region {region_s * 1e3:.2f} ms (host wall {wall * 1e3:.2f} ms), "
         f"step kernels {step_s * 1e3:.2f} ms over {launches} launches; "
-        f"trace rows {len(trace)}, last E = {trace[-1, 2] + trace[-1, 3]:.6g}")
+        f"trace rows {len(trace)}, last E = {last_e}")
 
     if args.copy_calib:
         nbytes = 9 * n * n * 4

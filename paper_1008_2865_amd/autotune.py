@@ -12,8 +12,11 @@ import os
 
 import numpy as np
 
+# (tile_x, tile_y, tile_rows).  Tall tiles re-read fewer halo rows; short
+# ones keep a lattice of a few hundred rows spread over all 256 CUs.
 DEFAULT_CANDIDATES = [(256, 32, 1), (256, 16, 1), (128, 32, 1), (256, 32, 2), (128, 16, 1),
-                      (64, 32, 1), (256, 64, 2)]
+                      (64, 32, 1), (256, 64, 2), (256, 8, 1), (128, 8, 1), (256, 4, 1),
+                      (64, 4, 1), (256, 2, 1)]
 
 
 def cache_path():

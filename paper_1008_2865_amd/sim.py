@@ -96,7 +96,7 @@ class LBSim:
 
             if self.nx != self.ny:
                 raise ValueError("the structure factor is defined for square lattices")
-            self._sk = StructureFactor(self.nx)
+            self._sk = StructureFactor(self.nx, stream=self.stream)
         rho = self.moments(device=True)[0]
         return self._sk(rho, spectrum=spectrum)
 

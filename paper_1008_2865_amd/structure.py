@@ -12,7 +12,9 @@ from . import binding as B
 
 
 class StructureFactor:
-    def __init__(self, L):
+    def __init__(self, L, stream=None):
+        """stream: the torch CUDA stream to issue on (default: the current
+        stream); inputs must be ready on it."""
         import torch
 
         if not torch.cuda.is_available():
@@ -23,7 +25,7 @@ class StructureFactor:
         if nbytes == 0:
             raise B.LBError(B.LB_ERR_INVALID, f"no structure factor for L = {L} (5 <= L <= 2048)")
         self.nshell = B.lb_sk_shells(L)
-        self.stream = torch.cuda.current_stream()
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         self.ctx = B.lb_sk_init(L, self.workspace, nbytes, stream=self.stream.cuda_stream)
 

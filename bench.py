@@ -58,25 +58,73 @@ def measured_traffic(workload_key):
         return None
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(n, G1, G2, seed, target_s, steps=None):
-    """The oracle (FP64, OpenMP) on a bounded sample of the same workload."""
+    """The oracle (FP64, OpenMP) on a bounded sample of the same workload,
+    driven through the same lb_* call sequence as the GPU library (its
+    host-memory entry points); then a short single-thread sample."""
     import oracle as O
     from paper_1008_2865_amd import inputs
 
-    f = O.init(inputs.rho_noise(n, n, seed))
+    rho = inputs.rho_noise(n, n, seed)
+    lat = O.AbiLattice(rho, G1=G1, G2=G2)
     if steps is None:
-        f = O.step(f, 1, 1.0, 1.0, G1, G2)  # warm the threads and pages
+        lat.step(1)  # warm the threads and pages
         t0 = time.perf_counter()
-        f = O.step(f, 2, 1.0, 1.0, G1, G2)
+        lat.step(2)
         one = (time.perf_counter() - t0) / 2
         steps = int(max(1, min(5000, target_s / max(one, 1e-6))))
     t0 = time.perf_counter()
-    O.step(f, steps, 1.0, 1.0, G1, G2)
+    lat.step(steps)
     dt = time.perf_counter() - t0
+    threads = O.threads()
+    # Single thread, about a fifth of the time budget.
+    O.set_threads(1)
+    t1 = time.perf_counter()
+    lat.step(1)
+    one1 = time.perf_counter() - t1
+    s1 = int(max(1, min(1000, 0.2 * target_s / max(one1, 1e-6))))
+    t1 = time.perf_counter()
+    lat.step(s1)
+    dt1 = time.perf_counter() - t1
+    O.set_threads(threads)
+    lat.close()
     return {"value": round(n * n * steps / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": O.threads(), "kind": "oracle",
-            "sample": f"{n}x{n} FP64 oracle, {steps} steps of the same workload "
-                      f"(r = G2/|G1|, seed {seed}), {dt:.1f} s wall"}
+            "cores": threads, "kind": "oracle",
+            "sample": f"{n}x{n} FP64 oracle through its lb_init/lb_step entry points, {steps} steps "
+                      f"of the same workload (r = G2/|G1|, seed {seed}), {dt:.1f} s wall on "
+                      f"{threads} threads",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "single_thread_mlups": round(n * n * s1 / dt1 / 1e6, 3),
+            "cpu_gbps_at_144_B_per_LU": round(n * n * steps / dt * 144 / 1e9, 2)}
+
+
+def copy_bandwidth(nbytes, reps=10):
+    """GB/s of torch's device copy of an nbytes buffer (read + write)."""
+    import torch
+
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    return 2.0 * nbytes * reps / (a.elapsed_time(b) / 1e3) / 1e9
 
 
 def main():
@@ -195,6 +243,7 @@ def main():
     achieved = bpl * sites / avg_launch / 1e9
     workload_key = f"{n}x{n} {args.storage} r={args.r} tile {tx}x{ty}x{tr}"
     traffic = measured_traffic(workload_key)
+    copy_gbps = copy_bandwidth(bpl // 2 * sites)
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -226,6 +275,9 @@ def main():
             "kernel": "k_step (fused pull-stream + two-belt force + BGK collide)",
             "algorithmic_bytes_per_launch": bpl * sites,
             "avg_launch_us": round(avg_launch * 1e6, 3),
+            "traffic_gbps": round(traffic / avg_launch / 1e9, 1) if traffic else None,
+            "device_copy_gbps": round(copy_gbps, 1),
+            "frac_of_device_copy": round(achieved / copy_gbps, 4),
         },
     }
     if args.cpu_seconds > 0 or args.cpu_steps:

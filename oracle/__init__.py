@@ -31,6 +31,7 @@ def lib(precision="f64"):
         L.orc_tables.argtypes = [_vp, _vp, _vp, _vp, _dbl, _dbl]
         L.orc_real_bytes.restype = ctypes.c_int
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_init.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp]
         L.orc_moments.argtypes = [_i64, _i64, _vp, _vp, _vp, _vp]
         L.orc_psi.argtypes = [_i64, _dbl, _vp, _vp]
@@ -61,6 +62,11 @@ def _field(a, dt):
 def threads(precision="f64"):
     """OpenMP threads the oracle's loops run on."""
     return lib(precision).orc_threads()
+
+
+def set_threads(n, precision="f64"):
+    """Run the oracle's loops on n OpenMP threads."""
+    lib(precision).orc_set_threads(int(n))
 
 
 def d2q9():
@@ -166,3 +172,107 @@ def run(f, nsteps, tau, rho0, G1, G2, log_every, precision="f64"):
     if rows < 0:
         raise MemoryError("orc_run")
     return f, trace[:rows]
+
+
+# ---------------------------------------------------------------------------
+# The lb_* entry points of the oracle libraries (oracle_abi.c): the same call
+# sequence as the GPU library, on host memory.
+# ---------------------------------------------------------------------------
+class Params(ctypes.Structure):
+    """The interface's parameter block (layout of the C declaration)."""
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
+                ("storage", ctypes.c_int32), ("log_every", ctypes.c_int32),
+                ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("trace_cap", ctypes.c_int64),
+                ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
+                ("G1", ctypes.c_double), ("G2", ctypes.c_double),
+                ("rho_ref", ctypes.c_double)]
+
+
+_ABI = {}
+
+
+def abi(precision="f64"):
+    """The oracle library with the lb_* signatures set."""
+    if precision not in _ABI:
+        L = lib(precision)
+        P = ctypes.POINTER(Params)
+        sig = {
+            "lb_workspace_bytes": (ctypes.c_size_t, [P]),
+            "lb_validate": (ctypes.c_int, [P]),
+            "lb_launch_shape": (ctypes.c_int, [P, _vp, _vp, _vp, _vp]),
+            "lb_init": (ctypes.c_int, [ctypes.POINTER(_vp), P, _vp, ctypes.c_size_t,
+                                       _vp, _vp, _vp, ctypes.c_int, _vp]),
+            "lb_step": (ctypes.c_int, [_vp, _i64]),
+            "lb_moments": (ctypes.c_int, [_vp, _vp, _vp, _vp, ctypes.c_int]),
+            "lb_pseudo_energy": (ctypes.c_int, [_vp, _vp]),
+            "lb_trace": (ctypes.c_int, [_vp, _vp, _i64, _vp]),
+            "lb_time": (ctypes.c_int, [_vp, _vp]),
+            "lb_get_state": (ctypes.c_int, [_vp, _vp, ctypes.c_int]),
+            "lb_set_state": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _i64]),
+            "lb_tables": (ctypes.c_int, [P, _vp, _vp, _vp, _vp]),
+            "lb_destroy": (ctypes.c_int, [_vp]),
+            "lb_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _ABI[precision] = L
+    return _ABI[precision]
+
+
+class AbiLattice:
+    """One lattice driven through the oracle's lb_* entry points."""
+
+    def __init__(self, rho_init, *, G1, G2, tau=1.0, rho0=1.0, log_every=0, trace_cap=0,
+                 precision="f64"):
+        self.L = abi(precision)
+        self.precision = precision
+        rho = np.ascontiguousarray(rho_init, dtype=np.float64)
+        self.ny, self.nx = rho.shape
+        self.p = Params(nx=self.nx, ny=self.ny, storage=0 if precision == "f64" else 1,
+                        log_every=log_every, trace_cap=trace_cap, tau=tau, rho0=rho0, G1=G1, G2=G2)
+        nbytes = self.L.lb_workspace_bytes(ctypes.byref(self.p))
+        if nbytes == 0:
+            raise ValueError(self.L.lb_last_error().decode())
+        self.ws = np.zeros(nbytes, np.uint8)
+        self.ctx = _vp()
+        self._ok(self.L.lb_init(ctypes.byref(self.ctx), ctypes.byref(self.p), self.ws.ctypes.data,
+                                nbytes, rho.ctypes.data, None, None, 0, None))
+        self.trace_cap = trace_cap
+
+    def _ok(self, rc):
+        if rc != 0:
+            raise RuntimeError(f"oracle lb_* call failed ({rc}): {self.L.lb_last_error().decode()}")
+        return rc
+
+    def step(self, n):
+        self._ok(self.L.lb_step(self.ctx, n))
+
+    def moments(self):
+        out = [np.empty((self.ny, self.nx)) for _ in range(3)]
+        self._ok(self.L.lb_moments(self.ctx, *[a.ctypes.data for a in out], 0))
+        return tuple(out)
+
+    def pseudo_energy(self):
+        out = np.empty(6)
+        self._ok(self.L.lb_pseudo_energy(self.ctx, out.ctypes.data))
+        return out
+
+    def trace(self):
+        out = np.empty((max(self.trace_cap, 1), 6))
+        n = ctypes.c_int64()
+        self._ok(self.L.lb_trace(self.ctx, out.ctypes.data, self.trace_cap, ctypes.byref(n)))
+        return out[:n.value].copy()
+
+    def get_state(self):
+        out = np.empty((9, self.ny, self.nx), _DT[self.precision])
+        self._ok(self.L.lb_get_state(self.ctx, out.ctypes.data, 0))
+        return out
+
+    def close(self):
+        if self.ctx:
+            self.L.lb_destroy(self.ctx)
+            self.ctx = _vp()

@@ -164,6 +164,9 @@ int orc_real_bytes(void) { return (int)sizeof(real); }
 /* Threads the OpenMP loops of this library use (for timing reports). */
 int orc_threads(void) { return omp_get_max_threads(); }
 
+/* Set that number (single-thread timings). */
+void orc_set_threads(int n) { omp_set_num_threads(n > 0 ? n : 1); }
+
 /* ---------------------------------------------------------------------------
  * Section II: equilibrium, moments, pseudopotential.
  * ------------------------------------------------------------------------ */

@@ -113,6 +113,28 @@ def test_fields_bit_identical_across_launch_shapes(storage):
         assert np.array_equal(s.view(word), states[0].view(word))
 
 
+def test_same_call_sequence_on_gpu_and_oracle():
+    # The oracle libraries export the same entry points on host memory: drive
+    # both with one call sequence (chunked steps, logging, moments, state).
+    G1, G2 = R01
+    rho0 = inputs.rho_noise(64, 48, 6)
+    gpu = LBSim(rho0, G1=G1, G2=G2, tau=0.9, storage="f64", log_every=25, trace_cap=16)
+    cpu = O.AbiLattice(rho0, G1=G1, G2=G2, tau=0.9, log_every=25, trace_cap=16)
+    for n in (10, 40, 75, 0, 25):
+        gpu.step(n)
+        cpu.step(n)
+    tg, tc = gpu.trace(), cpu.trace()
+    assert tg.shape == tc.shape == (7, 6) and np.array_equal(tg[:, 0], tc[:, 0])
+    assert float(np.max(np.abs(tg[:, 1:] - tc[:, 1:]) / np.abs(tc[:, 1:]))) <= 1e-11
+    for a, b in zip(gpu.moments(), cpu.moments()):
+        assert dmax(a, b) <= 1e-10
+    assert dmax(gpu.get_state(), cpu.get_state()) <= 1e-10
+    e_g, e_c = gpu.pseudo_energy(), cpu.pseudo_energy()
+    assert e_g[0] == e_c[0] == 150 and np.all(np.abs(e_g[1:] - e_c[1:]) <= 1e-11 * np.abs(e_c[1:]))
+    gpu.close()
+    cpu.close()
+
+
 def test_velocity_and_energy_match_oracle():
     G1, G2 = R01
     rng = np.random.default_rng(8)

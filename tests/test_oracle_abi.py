@@ -1,0 +1,94 @@
+"""The oracle behind the interface's lb_* entry points (oracle/oracle_abi.c).
+
+The oracle libraries export the same entry points as the GPU library, on
+host memory, so a test (or the benchmark's CPU leg) can drive either with
+one call sequence.  These checks hold the layer to the oracle's own
+functions (which the other oracle tests pin to the paper) and to the
+interface's rules: trace indexing, failure without side effects, host-only
+memory.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1008_2865_amd import inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def core_symbols():
+    """The single-lattice entry points of include/lb.h (before the batch section)."""
+    text = open(os.path.join(ROOT, "include", "lb.h")).read()
+    text = text.split("Batches:")[0]
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lb_[a-z_]+)\s*\(", text)))
+
+
+@pytest.mark.parametrize("precision", ["f64", "f32"])
+def test_exports_the_single_lattice_interface(precision):
+    L = O.abi(precision)
+    names = core_symbols()
+    assert len(names) == 14
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_call_sequence_equals_the_oracle_run():
+    G1, G2 = inputs.couplings(0.1)
+    rho0 = inputs.rho_noise(64, 64, 1)
+    lat = O.AbiLattice(rho0, G1=G1, G2=G2, log_every=50, trace_cap=41)
+    for n in (7, 493, 500):        # logging rides on the steps that leave t = 0, 50, ...
+        lat.step(n)
+    tr = lat.trace()               # t = 1000 is recorded here
+    f, tr_o = O.run(O.init(rho0), 1000, 1.0, 1.0, G1, G2, 50)
+    assert tr.shape == (21, 6) and np.array_equal(tr, tr_o)
+    assert np.array_equal(lat.get_state(), f)
+    rho, ux, uy = lat.moments()
+    assert np.array_equal(rho, f.sum(axis=0))
+    e = lat.pseudo_energy()
+    assert e[0] == 1000 and np.array_equal(e[1:], tr_o[-1, 1:])
+    lat.close()
+
+
+def test_failures_change_nothing():
+    G1, G2 = inputs.couplings(0.1)
+    lat = O.AbiLattice(inputs.rho_noise(16, 12, 2), G1=G1, G2=G2, log_every=5, trace_cap=2)
+    L = lat.L
+    lat.step(5)                    # row for t = 0
+    before = lat.get_state()
+    assert L.lb_step(lat.ctx, 6) == -4          # would need rows for t = 5 and 10
+    assert np.array_equal(lat.get_state(), before)
+    t = ctypes.c_int64()
+    assert L.lb_time(lat.ctx, ctypes.byref(t)) == 0 and t.value == 5
+    assert L.lb_step(lat.ctx, -1) == -1
+    out = np.empty(6)
+    assert L.lb_moments(lat.ctx, out.ctypes.data, None, None, 1) == -1   # device memory: refused
+    lat.close()
+    p = O.Params(nx=4, ny=16, storage=0, tau=1.0, rho0=1.0, G1=G1, G2=G2)
+    assert L.lb_workspace_bytes(ctypes.byref(p)) == 0 and L.lb_validate(ctypes.byref(p)) == -1
+    p = O.Params(nx=16, ny=16, storage=1, tau=1.0, rho0=1.0, G1=G1, G2=G2)
+    assert L.lb_validate(ctypes.byref(p)) == -1  # the FP64 library computes FP64 only
+    assert O.abi("f32").lb_validate(ctypes.byref(p)) == 0
+
+
+def test_state_round_trip_and_tables():
+    G1, G2 = inputs.couplings(0.05)
+    lat = O.AbiLattice(inputs.rho_noise(20, 15, 4), G1=G1, G2=G2)
+    lat.step(30)
+    s = lat.get_state()
+    lat.step(10)
+    assert lat.L.lb_set_state(lat.ctx, s.ctypes.data, 0, 30) == 0
+    lat.step(10)
+    ref = O.step(s.copy(), 10, 1.0, 1.0, G1, G2)
+    assert np.array_equal(lat.get_state(), ref)
+    cx, cy = np.empty(24, np.int8), np.empty(24, np.int8)
+    K, KE = np.empty(24), np.empty(25)
+    assert lat.L.lb_tables(ctypes.byref(lat.p), cx.ctypes.data, cy.ctypes.data, K.ctypes.data,
+                           KE.ctypes.data) == 0
+    tc, tcy, tK, tKE = O.tables(G1, G2)
+    assert np.array_equal(cx, tc) and np.array_equal(K, tK) and np.array_equal(KE, tKE)
+    lat.close()

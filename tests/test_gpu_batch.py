@@ -89,3 +89,30 @@ def test_batch_members_cannot_be_stepped_alone():
     assert e.value.code == B.LB_ERR_STATE
     assert m.t == 5 and m.trace().shape == (2, 6)
     batch.close()
+
+
+def test_full_sweep_sampled_lattices_against_oracle():
+    """The 96-lattice sweep (36.8 M sites) in one launch per step, FP32,
+    128 x 32 tiles with two rows per stage (the tuned shape): after a few
+    steps the smallest, a middle and the largest lattice match the oracle
+    pointwise."""
+    spec = inputs.batched_lattices()
+    lats = []
+    for d in spec:
+        G1, G2 = inputs.couplings(d["r"])
+        lats.append(dict(rho_init=inputs.rho_noise(d["n"], d["n"], d["seed"]), G1=G1, G2=G2,
+                         tile_y=32))
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch = LBBatch(lats, storage="f32", tile_x=128, tile_rows=2, log_every=5, max_steps=5)
+        batch.step(5)
+        order = sorted(range(len(spec)), key=lambda k: spec[k]["n"])
+        for k in (order[0], order[len(order) // 2], order[-1]):
+            L = lats[k]
+            fo = O.step(O.init(L["rho_init"]), 5, 1.0, 1.0, L["G1"], L["G2"])
+            rho = batch[k].moments()[0]
+            assert float(np.max(np.abs(rho - fo.sum(axis=0)))) <= 2e-6, k
+            tr = batch[k].trace()
+            eo = O.observables(fo, 1.0, L["G1"], L["G2"])
+            assert tr.shape == (2, 6) and np.all(np.abs(tr[1, 1:] - eo) <= 1e-5 * np.abs(eo)), k
+        batch.close()

@@ -195,18 +195,69 @@ def test_f32_spinodal_regime_against_twin_error():
     sim.close()
 
 
-def test_f32_full_size_launch_configuration():
-    # 2048x2048, the benchmark's launch shape: a few steps against the oracle.
-    G1, G2 = R01
-    rho0 = inputs.rho_noise(2048, 2048, 1)
+@pytest.mark.parametrize("r,seed", [(0.0, 1), (0.05, 2), (0.1, 3)])
+def test_f32_full_size_launch_configuration(r, seed):
+    # 2048x2048 in the benchmark's launch shape (256 x 32 tiles, two-row
+    # lookahead), the three coupling ratios and seeds of the 2048^2 sweep:
+    # a few steps against the oracle (pointwise, before any amplification).
+    G1, G2 = inputs.couplings(r)
+    rho0 = inputs.rho_noise(2048, 2048, seed)
     fo = oracle_f(rho0, 5, G1, G2)
     sim = gpu_run(rho0, 5, G1, G2, storage="f32", log_every=5)
+    assert sim.launch_shape()[:3] == (256, 32, 1)
     rho, _, _ = sim.moments()
     assert dmax(rho, fo.sum(axis=0)) <= 2e-6
     tr = sim.trace()
     eo = O.observables(fo, 1.0, G1, G2)
     assert tr.shape[0] == 2 and tr[1, 0] == 5
     assert np.all(np.abs(tr[1, 1:] - eo) <= 1e-5 * np.abs(eo))
+    sim.close()
+
+
+def test_f32_full_size_first_1000_steps():
+    # The 2048^2 workload (r = 0.1, seed 1) through its first 1000 steps,
+    # energies every 100: the spinodal amplification makes pointwise FP32
+    # errors those of single-precision arithmetic itself, bounded by three
+    # times the oracle's own FP32 twin; energies within 1e-4, mass drift
+    # within 1e-6.
+    G1, G2 = R01
+    rho0 = inputs.rho_noise(2048, 2048, 1)
+    fo, tr_o = O.run(O.init(rho0), 1000, 1.0, 1.0, G1, G2, 100)
+    ft = oracle_f(rho0, 1000, G1, G2, precision="f32")
+    d_twin = np.abs(ft.sum(axis=0).astype(np.float64) - fo.sum(axis=0))
+    sim = gpu_run(rho0, 1000, G1, G2, storage="f32", log_every=100)
+    rho, _, _ = sim.moments()
+    d = np.abs(rho - fo.sum(axis=0))
+    print(f"2048^2 FP32 after 1000 steps: max|drho| {d.max():.3e} (twin {d_twin.max():.3e}), "
+          f"mean {d.mean():.3e} (twin {d_twin.mean():.3e})", flush=True)
+    # By t = 1000 droplets have formed on this lattice: a single interface
+    # displaced by a site makes an O(1) pointwise difference, so the mean is
+    # bounded too.
+    assert d.max() <= max(3 * d_twin.max(), 1e-5)
+    assert d.mean() <= max(3 * d_twin.mean(), 1e-6)
+    tr = sim.trace()
+    assert tr.shape == tr_o.shape == (11, 6)
+    E, Eo = tr[:, 2] + tr[:, 3], tr_o[:, 2] + tr_o[:, 3]
+    assert float(np.max(np.abs(E - Eo) / np.abs(Eo))) <= 1e-4
+    assert float(np.max(np.abs(tr[:, 1] - tr[0, 1])) / tr[0, 1]) <= 1e-6
+    sim.close()
+
+
+def test_f16dev_full_size_launch_configuration():
+    # 8192x8192 half-precision storage in the benchmark's launch shape: a few
+    # steps against the oracle, within the half storage's resolution of the
+    # deviation (about 1e-3 of the populations).
+    G1, G2 = R01
+    rho0 = inputs.rho_noise(8192, 8192, 1)
+    fo = oracle_f(rho0, 5, G1, G2)
+    sim = gpu_run(rho0, 5, G1, G2, storage="f16dev", log_every=5)
+    assert sim.launch_shape()[:3] == (256, 32, 1)
+    rho, _, _ = sim.moments()
+    assert dmax(rho, fo.sum(axis=0)) <= 2e-3
+    tr = sim.trace()
+    eo = O.observables(fo, 1.0, G1, G2)
+    assert abs(tr[1, 1] - eo[0]) <= 1e-5 * eo[0]                  # mass
+    assert abs((tr[1, 2] + tr[1, 3]) - (eo[1] + eo[2])) <= 1e-3 * abs(eo[1] + eo[2])
     sim.close()
 
 

@@ -193,3 +193,14 @@ def test_structure_factor_host_side():
         with pytest.raises(B.LBError) as e:
             B.lb_sk_init(64, 256, B.lb_sk_workspace_bytes(64))
         assert e.value.code == B.LB_ERR_HIP
+
+
+@pytest.mark.parametrize("n,shape", [
+    (2048, (256, 32, 1, 512)),   # the tallest tile that keeps >= 512 workgroups
+    (1024, (256, 8, 1, 512)),
+    (512, (256, 2, 1, 512)),
+    (8192, (256, 32, 1, 8192)),
+    (100, (64, 2, 1, 100)),      # small lattices: 2-row tiles at least
+])
+def test_default_launch_shape(n, shape):
+    assert B.lb_launch_shape(B.make_params(n, n)) == shape

@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0
 BYTES_PER_LU = {"f64": 144, "f32": 72, "f16dev": 36}
 METRIC = "MLUPS and achieved HBM GB/s (two-belt D2Q9 step); adjoint/forward time ratio"
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_step_f32_2048_traffic.txt")
+TRAFFIC_FILES = [os.path.join(ROOT, "profiles", "k_step2_f32_2048_traffic.txt"),
+                 os.path.join(ROOT, "profiles", "k_step_f32_2048_traffic.txt")]
 KERNEL_SRC = os.path.join(ROOT, "paper_1008_2865_amd", "csrc", "lb_kernels.hip")
 
 
@@ -40,22 +41,24 @@ def kernel_source_hash():
 
 
 def measured_traffic(workload_key):
-    """HBM bytes per step-kernel launch from the committed counter summary,
-    or None if it is missing, for another workload, or older than the kernel."""
-    if not os.path.exists(TRAFFIC_FILE):
-        return None
-    kv = {}
-    with open(TRAFFIC_FILE) as fh:
-        for line in fh:
-            if ":" in line and not line.startswith("#"):
-                k, v = line.split(":", 1)
-                kv[k.strip()] = v.strip()
-    if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload_key:
-        return None
-    try:
-        return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+    """HBM bytes per launch of the dominant kernel from a committed counter
+    summary, or None if none is for this workload and the current kernel."""
+    for path in TRAFFIC_FILES:
+        if not os.path.exists(path):
+            continue
+        kv = {}
+        with open(path) as fh:
+            for line in fh:
+                if ":" in line and not line.startswith("#"):
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha256") != kernel_source_hash() or kv.get("workload") != workload_key:
+            continue
+        try:
+            return float(kv["fetch_bytes_per_launch"]) + float(kv["write_bytes_per_launch"])
+        except (KeyError, ValueError):
+            continue
+    return None
 
 
 def cpu_model():
@@ -140,6 +143,8 @@ def main():
     ap.add_argument("--tile-x", type=int, default=0)
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--tile-rows", type=int, default=0)
+    ap.add_argument("--steps-per-launch", type=int, default=0,
+                    help="0: library choice; 1; 2: plain FP32 steps two per launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="oracle sample length; 0 skips the CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=None)
@@ -181,11 +186,14 @@ def main():
     rho0 = inputs.rho_noise(n, n, args.seed)
     total = W + K
     sim = LBSim(rho0, G1=G1, G2=G2, storage=args.storage, log_every=le,
-                max_steps=total + le, tile_x=args.tile_x, tile_y=args.tile_y,
-                tile_rows=args.tile_rows)
+                max_steps=total + 2 * le + 1, tile_x=args.tile_x, tile_y=args.tile_y,
+                tile_rows=args.tile_rows, steps_per_launch=args.steps_per_launch)
     tx, ty, tr, nb = sim.launch_shape()
+    tx2, ty2, nb2 = B.lb_two_step_shape(sim.p)
+    two = tx2 > 0
     log(f"bench: {n}x{n} {args.storage}, r={args.r}, tile {tx}x{ty}x{tr}, {nb} workgroups, "
-        f"warmup {W}, steps {K}, log every {le}")
+        + (f"two-step tile {tx2}x{ty2} ({tx2 - 6} columns out), {nb2} workgroups, " if two else "")
+        + f"warmup {W}, steps {K}, log every {le}")
     moments = [torch.empty((n, n), dtype=torch.float64, device="cuda") for _ in range(3)]
 
     def run(nsteps, pairs=None):
@@ -224,8 +232,24 @@ def main():
     trace = sim.trace()
     last_e = f"{trace[-1, 2] + trace[-1, 3]:.6g}" if len(trace) else "n/a"
     log(f"bench: region {region_s * 1e3:.2f} ms (host wall {wall * 1e3:.2f} ms), "
-        f"step kernels {step_s * 1e3:.2f} ms over {launches} launches; "
+        f"step chunks {step_s * 1e3:.2f} ms over {launches} steps; "
         f"trace rows {len(trace)}, last E = {last_e}")
+
+    # The dominant kernel on its own: plain steps between two log points
+    # (two per launch where the library runs them so), timed with HIP events
+    # on the library's stream.
+    if le and sim.t % le == 0:
+        sim.step(1)  # the logged step leaving this log point
+    probe = 400 if not le else min(400, (le - 1 - sim.t % le) // 2 * 2)
+    pa = torch.cuda.Event(enable_timing=True)
+    pb = torch.cuda.Event(enable_timing=True)
+    pa.record()
+    sim.step(probe)
+    pb.record()
+    torch.cuda.synchronize()
+    per_launch_steps = 2 if two else 1
+    launches_probe = probe // per_launch_steps
+    avg_launch = pa.elapsed_time(pb) / 1e3 / launches_probe
 
     if args.copy_calib:
         nbytes = 9 * n * n * 4
@@ -239,11 +263,14 @@ def main():
     sites = n * n
     bpl = BYTES_PER_LU[args.storage]
     value = sites * K / region_s / 1e6
-    avg_launch = step_s / launches
-    achieved = bpl * sites / avg_launch / 1e9
-    workload_key = f"{n}x{n} {args.storage} r={args.r} tile {tx}x{ty}x{tr}"
+    alg_bytes = bpl * sites * per_launch_steps
+    achieved = alg_bytes / avg_launch / 1e9
+    workload_key = (f"{n}x{n} {args.storage} r={args.r} "
+                    + (f"two-step tile {tx2}x{ty2}" if two else f"tile {tx}x{ty}x{tr}"))
     traffic = measured_traffic(workload_key)
     copy_gbps = copy_bandwidth(bpl // 2 * sites)
+    kernel = ("k_step2 (two fused pull-stream + two-belt force + BGK collide steps per launch)"
+              if two else "k_step (fused pull-stream + two-belt force + BGK collide)")
     out = {
         "metric": METRIC,
         "value": round(value, 1),
@@ -263,6 +290,8 @@ def main():
                         f"moments + pseudo-energy every {le} steps",
             "nx": n, "ny": n, "storage": args.storage, "G1": G1, "G2": G2, "tau": 1.0,
             "log_every": le, "tile_x": tx, "tile_y": ty, "tile_rows": tr, "workgroups": nb,
+            "steps_per_launch": per_launch_steps,
+            "two_step_tile": [tx2, ty2] if two else None, "two_step_workgroups": nb2 if two else None,
         },
         "effective_gbps": round(value * bpl / 1e3, 1),
         "roofline": {
@@ -272,9 +301,11 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / PEAK_HBM_GBPS, 4),
             "traffic": traffic,
-            "kernel": "k_step (fused pull-stream + two-belt force + BGK collide)",
-            "algorithmic_bytes_per_launch": bpl * sites,
+            "kernel": kernel,
+            "algorithmic_bytes_per_launch": alg_bytes,
+            "lattice_updates_per_launch": sites * per_launch_steps,
             "avg_launch_us": round(avg_launch * 1e6, 3),
+            "launches_timed": launches_probe,
             "traffic_gbps": round(traffic / avg_launch / 1e9, 1) if traffic else None,
             "device_copy_gbps": round(copy_gbps, 1),
             "frac_of_device_copy": round(achieved / copy_gbps, 4),

@@ -74,7 +74,10 @@ typedef struct lb_params {
     int32_t tile_y;      /* rows per workgroup: 0 (library choice) or 1..4096    */
     int32_t tile_rows;   /* rows a workgroup updates per pipeline stage:
                             0 (library choice), 1 or 2                           */
-    int32_t reserved;    /* must be 0                                            */
+    int32_t steps_per_launch; /* 0 (library choice), 1, or 2: with 2 the plain
+                            steps of LB_F32 storage between log points run two
+                            per launch (temporal blocking); the fields are
+                            bit-identical to one step per launch               */
     int64_t trace_cap;   /* rows the trace can hold (>= 0)                       */
     double tau;          /* BGK relaxation time, > 0.5 (the paper uses 1)        */
     double rho0;         /* psi scale, > 0 (the paper fixes rho0 = 1)            */
@@ -95,6 +98,13 @@ int lb_validate(const lb_params* p);
  * kernel (host only).  Any output may be NULL. */
 int lb_launch_shape(const lb_params* p, int32_t* tile_x, int32_t* tile_y,
                     int32_t* tile_rows, int32_t* blocks);
+
+/* Shape of the two-step launches for these parameters (host only): lanes
+ * per workgroup (each workgroup produces tile_x - 6 columns), rows per
+ * workgroup and workgroups; all three are 0 when plain steps run one per
+ * launch.  Any output may be NULL. */
+int lb_two_step_shape(const lb_params* p, int32_t* tile_x, int32_t* tile_y,
+                      int32_t* blocks);
 
 /* Create a context at t = 0 whose populations are the equilibrium
  * f_i^eq(rho_init, u_init) of section II (the paper starts from a fluid at

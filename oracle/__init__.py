@@ -183,7 +183,7 @@ class Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("log_every", ctypes.c_int32),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-                ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int64),
                 ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("G1", ctypes.c_double), ("G2", ctypes.c_double),
@@ -202,6 +202,7 @@ def abi(precision="f64"):
             "lb_workspace_bytes": (ctypes.c_size_t, [P]),
             "lb_validate": (ctypes.c_int, [P]),
             "lb_launch_shape": (ctypes.c_int, [P, _vp, _vp, _vp, _vp]),
+            "lb_two_step_shape": (ctypes.c_int, [P, _vp, _vp, _vp]),
             "lb_init": (ctypes.c_int, [ctypes.POINTER(_vp), P, _vp, ctypes.c_size_t,
                                        _vp, _vp, _vp, ctypes.c_int, _vp]),
             "lb_step": (ctypes.c_int, [_vp, _i64]),

@@ -47,7 +47,7 @@ enum { OK = 0, ERR_INVALID = -1, ERR_HIP = -2, ERR_NONFINITE = -3, ERR_STATE = -
 
 /* Layout of the interface's parameter block. */
 typedef struct {
-    int32_t nx, ny, storage, log_every, tile_x, tile_y, tile_rows, reserved;
+    int32_t nx, ny, storage, log_every, tile_x, tile_y, tile_rows, steps_per_launch;
     int64_t trace_cap;
     double tau, rho0, G1, G2, rho_ref;
 } params;
@@ -77,7 +77,8 @@ static int check(const params* p)
     if (p->storage != ORACLE_STORAGE)
         return fail(ERR_INVALID, "this oracle library computes with storage %d only", ORACLE_STORAGE);
     if (p->log_every < 0 || p->trace_cap < 0) return fail(ERR_INVALID, "negative log_every or trace_cap");
-    if (p->reserved != 0) return fail(ERR_INVALID, "reserved must be 0");
+    if (p->steps_per_launch < 0 || p->steps_per_launch > 2)
+        return fail(ERR_INVALID, "steps_per_launch must be 0, 1 or 2");
     if (!isfinite(p->tau) || !(p->tau > 0.5)) return fail(ERR_INVALID, "tau must be finite and > 0.5");
     if (!isfinite(p->rho0) || !(p->rho0 > 0.0)) return fail(ERR_INVALID, "rho0 must be finite and > 0");
     if (!isfinite(p->G1) || !isfinite(p->G2)) return fail(ERR_INVALID, "G1, G2 must be finite");
@@ -127,6 +128,17 @@ int lb_launch_shape(const params* p, int32_t* tile_x, int32_t* tile_y, int32_t* 
     if (tile_y) *tile_y = p->ny;
     if (tile_rows) *tile_rows = 1;
     if (blocks) *blocks = 1;
+    return OK;
+}
+
+/* Nor launches: no step is fused with another. */
+int lb_two_step_shape(const params* p, int32_t* tile_x, int32_t* tile_y, int32_t* blocks)
+{
+    int rc = check(p);
+    if (rc) return rc;
+    if (tile_x) *tile_x = 0;
+    if (tile_y) *tile_y = 0;
+    if (blocks) *blocks = 0;
     return OK;
 }
 

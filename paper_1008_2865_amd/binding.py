@@ -33,7 +33,7 @@ class lb_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32),
                 ("storage", ctypes.c_int32), ("log_every", ctypes.c_int32),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32),
-                ("tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("tile_rows", ctypes.c_int32), ("steps_per_launch", ctypes.c_int32),
                 ("trace_cap", ctypes.c_int64),
                 ("tau", ctypes.c_double), ("rho0", ctypes.c_double),
                 ("G1", ctypes.c_double), ("G2", ctypes.c_double),
@@ -53,6 +53,7 @@ SIGNATURES = {
     "lb_workspace_bytes": (ctypes.c_size_t, [_P]),
     "lb_validate": (ctypes.c_int, [_P]),
     "lb_launch_shape": (ctypes.c_int, [_P, _vp, _vp, _vp, _vp]),
+    "lb_two_step_shape": (ctypes.c_int, [_P, _vp, _vp, _vp]),
     "lb_init": (ctypes.c_int, [ctypes.POINTER(_vp), _P, _vp, ctypes.c_size_t,
                                _vp, _vp, _vp, ctypes.c_int, _vp]),
     "lb_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
@@ -123,9 +124,11 @@ def _ptr(a):
 
 
 def make_params(nx, ny, *, storage=LB_F32, tau=1.0, rho0=1.0, G1=-4.9, G2=0.0,
-                log_every=0, trace_cap=0, tile_x=0, tile_y=0, tile_rows=0, rho_ref=0.0):
+                log_every=0, trace_cap=0, tile_x=0, tile_y=0, tile_rows=0, rho_ref=0.0,
+                steps_per_launch=0):
     return lb_params(nx=nx, ny=ny, storage=storage, log_every=log_every,
-                     tile_x=tile_x, tile_y=tile_y, tile_rows=tile_rows, reserved=0,
+                     tile_x=tile_x, tile_y=tile_y, tile_rows=tile_rows,
+                     steps_per_launch=steps_per_launch,
                      trace_cap=trace_cap, tau=tau, rho0=rho0, G1=G1, G2=G2, rho_ref=rho_ref)
 
 
@@ -143,6 +146,14 @@ def lb_launch_shape(p):
     _check(lib().lb_launch_shape(ctypes.byref(p), ctypes.byref(tx), ctypes.byref(ty),
                                  ctypes.byref(tr), ctypes.byref(nb)))
     return tx.value, ty.value, tr.value, nb.value
+
+
+def lb_two_step_shape(p):
+    """(tile_x, tile_y, blocks) of the two-step launches, zeros if unused."""
+    tx, ty, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().lb_two_step_shape(ctypes.byref(p), ctypes.byref(tx), ctypes.byref(ty),
+                                   ctypes.byref(nb)))
+    return tx.value, ty.value, nb.value
 
 
 def lb_init(p, workspace, nbytes, rho_init, ux_init=None, uy_init=None,

@@ -106,7 +106,8 @@ int check_params(const lb_params* p)
         return fail(LB_ERR_INVALID, "tile_y must be in [0, 4096] (got %d)", p->tile_y);
     if (p->tile_rows < 0 || p->tile_rows > 2)
         return fail(LB_ERR_INVALID, "tile_rows must be 0, 1 or 2 (got %d)", p->tile_rows);
-    if (p->reserved != 0) return fail(LB_ERR_INVALID, "reserved must be 0");
+    if (p->steps_per_launch < 0 || p->steps_per_launch > 2)
+        return fail(LB_ERR_INVALID, "steps_per_launch must be 0, 1 or 2 (got %d)", p->steps_per_launch);
     if (!std::isfinite(p->tau) || !(p->tau > 0.5))
         return fail(LB_ERR_INVALID, "tau must be finite and > 0.5");
     if (!std::isfinite(p->rho0) || !(p->rho0 > 0.0))
@@ -151,6 +152,47 @@ Geom make_geom(const lb_params& p)
     return g;
 }
 
+// Geometry of the two-step launches: tiles of tile_x lanes that produce
+// tile_x - 6 columns (the first step also covers 3 columns each side).
+// Explicit tile_x / tile_y apply to both kernels; the library's choice is
+// 128 lanes and the tallest of 48, 32, 24, 16, 8 rows that still gives
+// 1400 workgroups: the first step's 7 extra rows per tile favour tall
+// tiles, a 2048^2 lattice wants enough tiles to fill the chip (measured on
+// MI355X, FP32, us/step: 2048^2 42.8 at 128 x 24 against 46.3 at 128 x 32
+// and 48.8 at 128 x 16; 4096^2 149.4 at 128 x 48).
+Geom make_geom2(const lb_params& p, const Geom& g)
+{
+    Geom g2 = g;
+    if (!p.tile_x) g2.tile_x = 128;
+    if (!p.tile_y) {
+        static const int kRows[] = {48, 32, 24, 16, 8};
+        const int tx = (p.nx + g2.tile_x - 7) / (g2.tile_x - 6);
+        g2.tile_y = 8;
+        for (int r : kRows)
+            if ((int64_t)tx * ((p.ny + r - 1) / r) >= 1400) {
+                g2.tile_y = r;
+                break;
+            }
+        if (g2.tile_y > p.ny) g2.tile_y = p.ny;
+    }
+    const int w = g2.tile_x - 6;
+    g2.tiles_x = (p.nx + w - 1) / w;
+    g2.blocks = g2.tiles_x * ((p.ny + g2.tile_y - 1) / g2.tile_y);
+    g2.rows_per_iter = 1;
+    return g2;
+}
+
+// Whether plain steps run two per launch: FP32 storage, and either asked
+// for (steps_per_launch = 2) or, by default, when the lattice is large
+// enough for tiles of 16 rows or more (below that the one-step kernel is as
+// fast or faster: 1024^2 16.6 us/step either way, 512^2 11.7 against 7.7).
+bool use_two(const lb_params& p, const Geom& g2)
+{
+    if (p.storage != LB_F32) return false;
+    if (p.steps_per_launch == 2) return true;
+    return p.steps_per_launch == 0 && g2.tile_y >= 16;
+}
+
 // Workspace layout, each region 256-byte aligned.
 struct Layout {
     size_t buf[2], partials, trace, scalars, staging, total;
@@ -176,6 +218,8 @@ Layout make_layout(const lb_params& p, const Geom& g)
 struct lb_ctx {
     lb_params p;
     Geom g;
+    Geom g2;     // two-step launches: tile_x lanes make tile_x - 6 columns
+    bool two;    // plain steps run two per launch where they can
     Coef coef;
     int device;
     hipStream_t stream;
@@ -291,6 +335,18 @@ int lb_launch_shape(const lb_params* p, int32_t* tile_x, int32_t* tile_y, int32_
     return LB_OK;
 }
 
+int lb_two_step_shape(const lb_params* p, int32_t* tile_x, int32_t* tile_y, int32_t* blocks)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    const Geom g2 = make_geom2(*p, make_geom(*p));
+    const bool on = use_two(*p, g2);
+    if (tile_x) *tile_x = on ? g2.tile_x : 0;
+    if (tile_y) *tile_y = on ? g2.tile_y : 0;
+    if (blocks) *blocks = on ? g2.blocks : 0;
+    return LB_OK;
+}
+
 int lb_tables(const lb_params* p, int8_t cx[24], int8_t cy[24], double K[24], double KE[25])
 {
     if (!p) return fail(LB_ERR_INVALID, "params is NULL");
@@ -359,6 +415,8 @@ int lb_init(lb_ctx** out, const lb_params* p, void* workspace, size_t bytes,
     lb_ctx* c = new lb_ctx();
     c->p = *p;
     c->g = g;
+    c->g2 = make_geom2(*p, g);
+    c->two = use_two(*p, c->g2);
     c->coef = make_coef(*p);
     c->device = dev;
     c->stream = st;
@@ -431,6 +489,16 @@ int lb_step(lb_ctx* c, int64_t n)
         const void* src = c->buf[c->cur];
         void* dst = c->buf[c->cur ^ 1];
         const bool log = le > 0 && c->t % le == 0 && c->last_logged != c->t;
+        // Two plain steps in one launch when neither state is logged.
+        if (c->two && !log && s + 1 < n && !(le > 0 && (c->t + 1) % le == 0)) {
+            c->coef.step = (uint32_t)c->t;
+            hipError_t e = lbk::launch_step2(c->p.storage, src, dst, c->g2, c->coef, c->stream);
+            if (e) return hip_fail(e, "two-step kernel launch");
+            c->cur ^= 1;
+            c->t += 2;
+            ++s;
+            continue;
+        }
         if (log) {
             if ((rc = energy_row(c, lbk::MODE_STEP_ENERGY, src, dst, c->trace + c->trace_rows * 6)))
                 return rc;

@@ -239,6 +239,90 @@ static_assert(((kCxPack >> 0) & 3u) == 1u && ((kCxPack >> 6) & 3u) == 0u &&
                   ((kCyPack >> 8) & 3u) == 0u && ((kCyPack >> 10) & 3u) == 2u,
               "speed packing");
 
+// psi at the 25 sites of the force stencil around one site, read from five
+// rows of a psi ring (rows y-2 .. y+2, LDS column c of the site), named by
+// direction: e1 = psi(x+1, y), ne = psi(x+1, y+1), e2n = psi(x+2, y+1), ...
+template <typename C>
+struct Stencil {
+    C p, e1, w1, n1, s1v, ne, nw, sw, se, e2, w2, n2, s2v, e2n, e2s, w2n, w2s, n2e, n2w, s2e, s2w,
+        ne2, nw2, sw2, se2;
+    __device__ __forceinline__ Stencil(const C* rm2, const C* rm1, const C* rc, const C* rp1,
+                                       const C* rp2, int c)
+        : p(rc[c]), e1(rc[c + 1]), w1(rc[c - 1]), n1(rp1[c]), s1v(rm1[c]), ne(rp1[c + 1]),
+          nw(rp1[c - 1]), sw(rm1[c - 1]), se(rm1[c + 1]), e2(rc[c + 2]), w2(rc[c - 2]),
+          n2(rp2[c]), s2v(rm2[c]), e2n(rp1[c + 2]), e2s(rm1[c + 2]), w2n(rp1[c - 2]),
+          w2s(rm1[c - 2]), n2e(rp2[c + 1]), n2w(rp2[c - 1]), s2e(rm2[c + 1]), s2w(rm2[c - 1]),
+          ne2(rp2[c + 2]), nw2(rp2[c - 2]), sw2(rm2[c - 2]), se2(rm2[c + 2])
+    {
+    }
+};
+
+// Force of eq. (FORCE) and the velocity-shift BGK collision at one site: R
+// the pre-collision populations, st the psi stencil around the site, Q the
+// post-collision populations; with kTape also the tape entry.  Every kernel
+// that updates a site calls this, so all of them round identically.
+template <bool kTape, typename C>
+__device__ __forceinline__ void site_collide(const C (&R)[9], const Stencil<C>& st, const CoefT<C>& k,
+                                             C (&Q)[9], C* tp)
+{
+#pragma clang fp contract(off)
+    // Multiply-adds are written out as fma and nothing else is contracted,
+    // so every kernel variant (launch shape, batched or not, one or two
+    // steps per launch) rounds each site's update identically.
+    const C p = st.p, e1 = st.e1, w1 = st.w1, n1 = st.n1, s1v = st.s1v, ne = st.ne, nw = st.nw,
+            sw = st.sw, se = st.se, e2 = st.e2, w2 = st.w2, n2 = st.n2, s2v = st.s2v, e2n = st.e2n,
+            e2s = st.e2s, w2n = st.w2n, w2s = st.w2s, n2e = st.n2e, n2w = st.n2w, s2e = st.s2e,
+            s2w = st.s2w, ne2 = st.ne2, nw2 = st.nw2, sw2 = st.sw2, se2 = st.se2;
+    // eq. (FORCE): F = -psi(x) sum_k K_k psi(x + c_k) c_k, links
+    // paired with their opposites.
+    const C sumx =
+        fma_c(k.K1, e1 - w1,
+              fma_c(k.K2, (ne + se) - (nw + sw),
+                    fma_c(k.K4x2, e2 - w2,
+                          fma_c(k.K5, fma_c((C)2, (e2n + e2s) - (w2n + w2s), (n2e + s2e) - (n2w + s2w)),
+                                k.K8x2 * ((ne2 + se2) - (nw2 + sw2))))));
+    const C sumy =
+        fma_c(k.K1, n1 - s1v,
+              fma_c(k.K2, (ne + nw) - (se + sw),
+                    fma_c(k.K4x2, n2 - s2v,
+                          fma_c(k.K5, fma_c((C)2, (n2e + n2w) - (s2e + s2w), (e2n + w2n) - (e2s + w2s)),
+                                k.K8x2 * ((ne2 + nw2) - (se2 + sw2))))));
+    const C Fx = -p * sumx;
+    const C Fy = -p * sumy;
+
+    // BGK collision at u_eq = (j + tau F) / rho.
+    const C rho = density(R);
+    const C jx = (R[1] - R[3]) + ((R[5] - R[7]) + (R[8] - R[6]));
+    const C jy = (R[2] - R[4]) + ((R[5] - R[7]) + (R[6] - R[8]));
+    if (kTape) {
+        tp[0] = rho;
+        tp[1] = jx;
+        tp[2] = jy;
+        tp[3] = p;
+    }
+    const C inv = rcp_c(rho);
+    const C ux = fma_c(k.tau, Fx, jx) * inv;
+    const C uy = fma_c(k.tau, Fy, jy) * inv;
+    // 1 - 1.5 u^2, and f_eq = w rho (1 - 1.5 u^2 + cu (3 + 4.5 cu)).
+    const C base = fma_c((C)-1.5, fma_c(ux, ux, uy * uy), (C)1);
+    const C r1 = rho * ((C)1 / (C)9);
+    const C r2 = rho * ((C)1 / (C)36);
+    const C om = k.omega;
+    auto feq = [&](C r, C cu) { return r * fma_c(cu, fma_c((C)4.5, cu, (C)3), base); };
+    auto relax = [&](C f, C fe) { return fma_c(om, fe - f, f); };
+    Q[1] = relax(R[1], feq(r1, ux));
+    Q[2] = relax(R[2], feq(r1, uy));
+    Q[3] = relax(R[3], feq(r1, -ux));
+    Q[4] = relax(R[4], feq(r1, -uy));
+    Q[5] = relax(R[5], feq(r2, ux + uy));
+    Q[6] = relax(R[6], feq(r2, uy - ux));
+    Q[7] = relax(R[7], feq(r2, -ux - uy));
+    Q[8] = relax(R[8], feq(r2, ux - uy));
+    // The collision conserves mass exactly; take the rest
+    // population from that so rounding cannot drift the mass.
+    Q[0] = rho - (((Q[1] + Q[3]) + (Q[2] + Q[4])) + ((Q[5] + Q[7]) + (Q[6] + Q[8])));
+}
+
 template <int J>
 using Ic = std::integral_constant<int, J>;
 
@@ -430,25 +514,19 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
             const C* rp2 = ring[slot(2)];
             const int c = tid + 2;
 
-            const C p = rc[c];
-            // psi(x + dx, y + dy), named by direction.
-            const C e1 = rc[c + 1], w1 = rc[c - 1], n1 = rp1[c], s1v = rm1[c];
-            const C ne = rp1[c + 1], nw = rp1[c - 1], sw = rm1[c - 1], se = rm1[c + 1];
-            const C e2 = rc[c + 2], w2 = rc[c - 2], n2 = rp2[c], s2v = rm2[c];
-            const C e2n = rp1[c + 2], e2s = rm1[c + 2], w2n = rp1[c - 2], w2s = rm1[c - 2];
-            const C n2e = rp2[c + 1], n2w = rp2[c - 1], s2e = rm2[c + 1], s2w = rm2[c - 1];
-            const C ne2 = rp2[c + 2], nw2 = rp2[c - 2], sw2 = rm2[c - 2], se2 = rm2[c + 2];
+            const Stencil<C> st(rm2, rm1, rc, rp1, rp2, c);
+            const C p = st.p;
 
             if (kEnergy && own) {
                 // No contraction here: the energies must round identically
                 // in every kernel variant that computes them (the step
                 // that also logs, the energy-only pass, the batched kernel).
 #pragma clang fp contract(off)
-                const C S1 = (e1 + w1) + (n1 + s1v);
-                const C S2 = (ne + sw) + (nw + se);
-                const C S4 = (e2 + w2) + (n2 + s2v);
-                const C S5 = ((e2n + w2s) + (e2s + w2n)) + ((n2e + s2w) + (n2w + s2e));
-                const C S8 = (ne2 + sw2) + (nw2 + se2);
+                const C S1 = (st.e1 + st.w1) + (st.n1 + st.s1v);
+                const C S2 = (st.ne + st.sw) + (st.nw + st.se);
+                const C S4 = (st.e2 + st.w2) + (st.n2 + st.s2v);
+                const C S5 = ((st.e2n + st.w2s) + (st.e2s + st.w2n)) + ((st.n2e + st.s2w) + (st.n2w + st.s2e));
+                const C S8 = (st.ne2 + st.sw2) + (st.nw2 + st.se2);
                 const C es = (C)0.5 * p * (k.KE0 * p + k.K1 * S1 + k.K2 * S2);
                 const C em = (C)0.5 * p * (k.K4 * S4 + k.K5 * S5 + k.K8 * S8);
                 aM += (double)density(R);
@@ -458,60 +536,8 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
             }
 
             if (kCollide) {
-                // Multiply-adds are written out as fma and nothing else is
-                // contracted, so every kernel variant (launch shape, batched
-                // or not) rounds each site's update identically.
-#pragma clang fp contract(off)
-                // eq. (FORCE): F = -psi(x) sum_k K_k psi(x + c_k) c_k, links
-                // paired with their opposites.
-                const C sumx =
-                    fma_c(k.K1, e1 - w1,
-                          fma_c(k.K2, (ne + se) - (nw + sw),
-                                fma_c(k.K4x2, e2 - w2,
-                                      fma_c(k.K5, fma_c((C)2, (e2n + e2s) - (w2n + w2s), (n2e + s2e) - (n2w + s2w)),
-                                            k.K8x2 * ((ne2 + se2) - (nw2 + sw2))))));
-                const C sumy =
-                    fma_c(k.K1, n1 - s1v,
-                          fma_c(k.K2, (ne + nw) - (se + sw),
-                                fma_c(k.K4x2, n2 - s2v,
-                                      fma_c(k.K5, fma_c((C)2, (n2e + n2w) - (s2e + s2w), (e2n + w2n) - (e2s + w2s)),
-                                            k.K8x2 * ((ne2 + nw2) - (se2 + sw2))))));
-                const C Fx = -p * sumx;
-                const C Fy = -p * sumy;
-
-                // BGK collision at u_eq = (j + tau F) / rho.
-                const C rho = density(R);
-                const C jx = (R[1] - R[3]) + ((R[5] - R[7]) + (R[8] - R[6]));
-                const C jy = (R[2] - R[4]) + ((R[5] - R[7]) + (R[6] - R[8]));
-                if (kTape) {
-                    tp[m][0] = rho;
-                    tp[m][1] = jx;
-                    tp[m][2] = jy;
-                    tp[m][3] = p;
-                }
-                const C inv = rcp_c(rho);
-                const C ux = fma_c(k.tau, Fx, jx) * inv;
-                const C uy = fma_c(k.tau, Fy, jy) * inv;
-                // 1 - 1.5 u^2, and f_eq = w rho (1 - 1.5 u^2 + cu (3 + 4.5 cu)).
-                const C base = fma_c((C)-1.5, fma_c(ux, ux, uy * uy), (C)1);
-                const C r1 = rho * ((C)1 / (C)9);
-                const C r2 = rho * ((C)1 / (C)36);
-                const C om = k.omega;
-                auto feq = [&](C r, C cu) { return r * fma_c(cu, fma_c((C)4.5, cu, (C)3), base); };
-                auto relax = [&](C f, C fe) { return fma_c(om, fe - f, f); };
-                C* Q = q[m];
-                Q[1] = relax(R[1], feq(r1, ux));
-                Q[2] = relax(R[2], feq(r1, uy));
-                Q[3] = relax(R[3], feq(r1, -ux));
-                Q[4] = relax(R[4], feq(r1, -uy));
-                Q[5] = relax(R[5], feq(r2, ux + uy));
-                Q[6] = relax(R[6], feq(r2, uy - ux));
-                Q[7] = relax(R[7], feq(r2, -ux - uy));
-                Q[8] = relax(R[8], feq(r2, ux - uy));
-                // The collision conserves mass exactly; take the rest
-                // population from that so rounding cannot drift the mass.
-                Q[0] = rho - (((Q[1] + Q[3]) + (Q[2] + Q[4])) + ((Q[5] + Q[7]) + (Q[6] + Q[8])));
-                if (m == 0) anchor = Q[0];
+                site_collide<kTape>(R, st, k, q[m], tp[m]);
+                if (m == 0) anchor = q[m][0];
             } else if (m == 0) {
                 anchor = p;
             }
@@ -600,6 +626,234 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
             partials[(int64_t)lb * 4 + tid] = s;
         }
     }
+}
+
+// ---------------------------------------------------------------------------
+// Two time steps per launch (temporal blocking) for plain single-precision
+// steps.  A tile of NT lanes produces NT - 6 output columns x0 .. x0+W-1 of
+// step t+2 for tile_y rows.  Level 1 is the one-step row walk above on the
+// NT columns x0-3 .. x0+NT-4 and on rows -3 .. nrows+2 of the tile (walk
+// order); its post-collision rows go to a 4-row LDS ring instead of memory.
+// Level 2 trails it: at walk row p it pulls the pre-collision populations of
+// row p-2 at t+1 from that ring (rows p-3 .. p-1, lanes l-1 .. l+1), stages
+// their psi, and, after a second barrier, applies the same force and
+// collision (site_collide, so every site rounds as in two one-step
+// launches) to row p-4, which it stores.  Global traffic per two steps is
+// one read and one write of the populations, plus halo rows and columns that
+// neighbouring tiles also read.
+// ---------------------------------------------------------------------------
+template <class P, int NT>
+__device__ __forceinline__ void
+step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
+           const Geom& g, const CoefT<typename P::C>& k, const int lb)
+{
+    using S = typename P::S;
+    using C = typename P::C;
+    static_assert(!P::kDev, "two-step launches store their first step in the arithmetic type");
+    constexpr int W = NT - 6;           // output columns of the tile
+    constexpr int LW = NT + 4;          // psi rings: lanes plus 2 columns each side
+    constexpr int kWaves = NT / 64;
+    constexpr int kHpw = 4 / kWaves;
+    constexpr int RS = 6, RS2 = 6, NF = 4;
+    __shared__ C ring[RS][LW];          // psi at t, level-1 rows p-2 .. p+3
+    __shared__ C ring2[RS2][LW];        // psi at t+1, rows p-7 .. p-2
+    __shared__ C fs[NF][9][NT];         // post-collision populations of step t+1
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wid = tid >> 6;
+    const int sx = lb % g.tiles_x;
+    const int sy = lb / g.tiles_x;
+    const int x0 = sx * W;              // first output column
+    const int y0 = sy * g.tile_y;
+    const int y1 = min(y0 + g.tile_y, g.ny);
+    const int dir = (sy & 1) ? -1 : 1;
+    const int ystart = dir > 0 ? y0 : y1 - 1;
+    const int nrows = y1 - y0;
+    const int nx = g.nx, ny = g.ny;
+    auto modn = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
+    // Lattice row of walk row r (r runs from -5 to nrows + 5).
+    auto wrow = [&](int r) { return modn(ystart + r * dir, ny); };
+
+    const S* pl[9];
+    S* pd[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        pl[i] = src + (int64_t)i * g.plane;
+        pd[i] = dst + (int64_t)i * g.plane;
+    }
+    const Offs<P> o(k.rho_ref);
+    CoefT<C> k2 = k;
+    k2.step = k.step + 1;
+
+    // Level-1 column of this lane (LDS column tid + 2): x0 - 3 + tid.
+    const int xb = x0 - 3;
+    const int xc = modn(xb + tid, nx);
+    const int xcm = xc == 0 ? nx - 1 : xc - 1;
+    const int xcp = xc == nx - 1 ? 0 : xc + 1;
+    // Level-2 output: lanes 3 .. 3+W-1, column x0 + tid - 3.
+    const bool own2 = tid >= 3 && tid < 3 + W && x0 + tid - 3 < nx;
+
+    // Halo columns of level 1 (xb-2, xb-1, xb+NT, xb+NT+1), gathered as in
+    // the one-step walk.
+    const int hj = lane < 9 * kHpw ? lane : 9 * kHpw - 1;
+    const int hi = hj % 9;
+    const int hcol = wid * kHpw + hj / 9;
+    const int hlds = hcol < 2 ? hcol : NT + hcol;
+    const int hgx = modn(xb - 2 + hlds - q_cx(hi), nx);
+    const S* hp = src + (int64_t)hi * g.plane + hgx;
+    const int hcy = q_cy(hi);
+    const C hoff = o.of(hi);
+    const int mcol = wid * kHpw + (lane < kHpw ? lane : 0);
+    const int mlds = mcol < 2 ? mcol : NT + mcol;
+    const int gbase = 9 * (lane < kHpw ? lane : 0);
+    auto halo_load = [&](int y) -> C {
+        const int ym = y == 0 ? ny - 1 : y - 1;
+        const int yp = y == ny - 1 ? 0 : y + 1;
+        const int r = (hcy > 0 ? ym : (hcy < 0 ? yp : y)) * g.pitch;
+        return P::ld(hp + r, hoff);
+    };
+    auto halo_psi = [&](C hv, int slot) {
+        C h[9];
+#pragma unroll
+        for (int m = 0; m < 9; ++m) h[m] = __shfl(hv, gbase + m, 64);
+        const C ps = psi_of(density(h), k);
+        if (lane < kHpw) ring[slot][mlds] = ps;
+    };
+
+    // Level-1 walk row p lives in Bf[(p + 3) % 4] (p >= -3); the level-2
+    // pre-collision row formed at iteration it in F2[(it + 2) % 4].
+    C Bf[4][9] = {};
+    C Hh[4] = {};
+    C F2[4][9] = {};
+
+    // Prologue: psi at t of walk rows -5 .. -1 into ring slots 0 .. 4 and
+    // the populations of rows -3 .. -1 into Bf[0 .. 2].
+    {
+        C T0[9], T1[9], hv[5];
+        pull<P>(pl, g, xc, xcm, xcp, wrow(-5), o, T0);
+        pull<P>(pl, g, xc, xcm, xcp, wrow(-4), o, T1);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) pull<P>(pl, g, xc, xcm, xcp, wrow(r - 3), o, Bf[r]);
+#pragma unroll
+        for (int r = 0; r < 5; ++r) hv[r] = halo_load(wrow(r - 5));
+        ring[0][tid + 2] = psi_of(density(T0), k);
+        ring[1][tid + 2] = psi_of(density(T1), k);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) ring[r + 2][tid + 2] = psi_of(density(Bf[r]), k);
+#pragma unroll
+        for (int r = 0; r < 5; ++r) halo_psi(hv[r], r);
+    }
+
+    // One iteration per level-1 row p = it - 3, it = 0 .. nrows + 6.
+    auto group = [&](auto Jc, int it, int s0) {
+        constexpr int J = decltype(Jc)::value;  // it % 4
+        const int p = it - 3;
+        // Lead row p + 3 (psi at t is needed up to row nrows + 4).
+        {
+            const int r = p + 3;
+            const int yl = r < nrows + 5 ? wrow(r) : wrow(p);
+            pull<P>(pl, g, xc, xcm, xcp, yl, o, Bf[(J + 3) % 4]);
+            Hh[(J + 3) % 4] = halo_load(yl);
+        }
+        __syncthreads();
+
+        // Level 2, part 1: pre-collision populations at t+1 of row p - 2
+        // (pulled from the ring rows p-3 .. p-1) and their psi.
+        if (p >= 0) {
+            // Formed here, collided two iterations later (which reads F2[J]).
+            C(&Fr)[9] = F2[(J + 2) % 4];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                // f_i(x, t+1) = f*_i(x - c_i): lattice row y - c_y is walk
+                // row r - c_y dir; lane l - c_x (clamped: lanes 0 and NT-1
+                // form values no output uses).
+                const int rr = p - 2 - q_cy(i) * dir;
+                const int li = min(max(tid - q_cx(i), 0), NT - 1);
+                Fr[i] = fs[(rr + 4) & 3][i][li];
+            }
+            ring2[(p - 2 + 12) % RS2][tid + 2] = psi_of(density(Fr), k2);
+        }
+
+        // Level 1: force and collision of row p into the ring of t+1.
+        C anchor = (C)0;
+        if (p <= nrows + 2) {
+            auto slot = [&](int dy) {
+                int v = s0 + 2 + dy * dir;
+                return v >= RS ? v - RS : v;
+            };
+            const Stencil<C> st(ring[slot(-2)], ring[slot(-1)], ring[slot(0)], ring[slot(1)],
+                                ring[slot(2)], tid + 2);
+            C q[9];
+            site_collide<false>(Bf[J % 4], st, k, q, (C*)nullptr);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) fs[(p + 4) & 3][i][tid] = q[i];
+            anchor = q[0];
+        }
+
+        // Stage psi at t of the lead row p + 3.
+        {
+            C(&NFr)[9] = Bf[(J + 3) % 4];
+            C& HF = Hh[(J + 3) % 4];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(NFr[i]) : "v"(anchor));
+            asm volatile("" : "+v"(HF) : "v"(anchor));
+            int sl = s0 + 5;
+            sl = sl >= RS ? sl - RS : sl;
+            ring[sl][tid + 2] = psi_of(density(NFr), k);
+            halo_psi(HF, sl);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        __syncthreads();
+
+        // Level 2, part 2: force and collision at t+1 of row q = p - 4, from
+        // psi rows q-2 .. q+2 at t+1; store.
+        const int qr = p - 4;
+        if (qr >= 0 && qr < nrows) {
+            auto s2 = [&](int dy) { return (qr + dy + 12) % RS2; };
+            // Walk rows are in walk order; psi row qr + dy is lattice row
+            // ystart + (qr + dy) dir, i.e. the stencil's y + dy dir.
+            const C* r_m2 = ring2[dir > 0 ? s2(-2) : s2(2)];
+            const C* r_m1 = ring2[dir > 0 ? s2(-1) : s2(1)];
+            const C* r_c = ring2[s2(0)];
+            const C* r_p1 = ring2[dir > 0 ? s2(1) : s2(-1)];
+            const C* r_p2 = ring2[dir > 0 ? s2(2) : s2(-2)];
+            const Stencil<C> st2(r_m2, r_m1, r_c, r_p1, r_p2, tid + 2);
+            C q2[9];
+            site_collide<false>(F2[J % 4], st2, k2, q2, (C*)nullptr);
+            if (own2) {
+                const int yq = wrow(qr);
+                store_site<P>(pd, yq * g.pitch + (x0 + tid - 3), q2, o, 0u);
+            }
+        }
+    };
+
+    auto step_slot = [](int s) { return s + 1 >= RS ? s + 1 - RS : s + 1; };
+    int s0 = 0;  // ring slot of level-1 walk row p - 2
+    const int iters = nrows + 7;
+#pragma unroll 1
+    for (int it = 0;;) {
+        group(Ic<0>{}, it, s0);
+        s0 = step_slot(s0);
+        if (++it >= iters) break;
+        group(Ic<1>{}, it, s0);
+        s0 = step_slot(s0);
+        if (++it >= iters) break;
+        group(Ic<2>{}, it, s0);
+        s0 = step_slot(s0);
+        if (++it >= iters) break;
+        group(Ic<3>{}, it, s0);
+        s0 = step_slot(s0);
+        if (++it >= iters) break;
+    }
+}
+
+template <class P, int NT>
+__global__ void __launch_bounds__(NT)
+k_step2(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst, Geom g,
+        CoefT<typename P::C> k)
+{
+    step2_tile<P, NT>(src, dst, g, k, xcd_remap(blockIdx.x, gridDim.x));
 }
 
 // One launch = one time step of one lattice: workgroup b updates logical
@@ -789,6 +1043,16 @@ hipError_t step_nt(int mode, const void* src, void* dst, const Geom& g,
 }
 
 template <class P, int NT>
+hipError_t step2_nt(const void* src, void* dst, const Geom& g, const Coef& c, hipStream_t s)
+{
+    using S = typename P::S;
+    const auto k = convert<typename P::C>(c);
+    hipLaunchKernelGGL((k_step2<P, NT>), dim3(g.blocks), dim3(NT), 0, s, static_cast<const S*>(src),
+                       static_cast<S*>(dst), g, k);
+    return hipGetLastError();
+}
+
+template <class P, int NT>
 hipError_t step_rpi(int mode, const void* src, void* dst, const Geom& g,
                     const Coef& c, double* partials, hipStream_t s)
 {
@@ -854,6 +1118,18 @@ hipError_t batch_p(int mode, int tile_x, int rpi, const BatchLaunch& a, hipStrea
 }
 
 }  // namespace
+
+hipError_t launch_step2(int storage, const void* src, void* dst, const Geom& g, const Coef& c,
+                        hipStream_t s)
+{
+    if (storage != ST_F32) return hipErrorInvalidValue;
+    switch (g.tile_x) {
+    case 64: return step2_nt<PF32, 64>(src, dst, g, c, s);
+    case 128: return step2_nt<PF32, 128>(src, dst, g, c, s);
+    case 256: return step2_nt<PF32, 256>(src, dst, g, c, s);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_step_batch(int storage, int mode, int tile_x, int rows_per_iter, int min_tile_y,
                              const BatchLattice* desc, const int32_t* tile_lattice, int tiles,

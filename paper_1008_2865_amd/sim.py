@@ -21,7 +21,7 @@ class LBSim:
 
     def __init__(self, rho_init, *, G1, G2, tau=1.0, rho0=1.0, storage="f32",
                  log_every=0, trace_cap=None, tile_x=0, tile_y=0, tile_rows=0, rho_ref=None,
-                 ux_init=None, uy_init=None, max_steps=None):
+                 ux_init=None, uy_init=None, max_steps=None, steps_per_launch=0):
         import torch
 
         if not torch.cuda.is_available():
@@ -46,7 +46,7 @@ class LBSim:
         st = STORAGE[storage]
         self.p = B.make_params(nx, ny, storage=st, tau=tau, rho0=rho0, G1=G1, G2=G2,
                                log_every=log_every, trace_cap=trace_cap, tile_x=tile_x,
-                               tile_y=tile_y, tile_rows=tile_rows,
+                               tile_y=tile_y, tile_rows=tile_rows, steps_per_launch=steps_per_launch,
                                rho_ref=(mean if rho_ref is None else rho_ref) if st == B.LB_F16DEV else 0.0)
         nbytes = B.lb_workspace_bytes(self.p)
         if nbytes == 0:

@@ -32,7 +32,7 @@ def core_symbols():
 def test_exports_the_single_lattice_interface(precision):
     L = O.abi(precision)
     names = core_symbols()
-    assert len(names) == 14
+    assert len(names) == 15
     for n in names:
         assert hasattr(L, n), n
 

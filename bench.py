@@ -144,7 +144,7 @@ def main():
     ap.add_argument("--tile-y", type=int, default=0)
     ap.add_argument("--tile-rows", type=int, default=0)
     ap.add_argument("--steps-per-launch", type=int, default=0,
-                    help="0: library choice; 1; 2: plain FP32 steps two per launch")
+                    help="0: library choice; 1; 2: plain FP32 or half-storage steps two per launch")
     ap.add_argument("--cpu-seconds", type=float, default=15.0,
                     help="oracle sample length; 0 skips the CPU baseline")
     ap.add_argument("--cpu-steps", type=int, default=None)

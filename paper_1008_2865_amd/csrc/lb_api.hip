@@ -182,15 +182,18 @@ Geom make_geom2(const lb_params& p, const Geom& g)
     return g2;
 }
 
-// Whether plain steps run two per launch: FP32 storage, and either asked
-// for (steps_per_launch = 2) or, by default, when the lattice is large
+// Whether plain steps run two per launch: FP32 or half storage when asked
+// for (steps_per_launch = 2); by default FP32 storage on lattices large
 // enough for tiles of 16 rows or more (below that the one-step kernel is as
 // fast or faster: 1024^2 16.6 us/step either way, 512^2 11.7 against 7.7).
+// Half storage stays at one step per launch by default: its step moves half
+// the bytes and is bound by arithmetic, not memory, so the two-step kernel
+// gains nothing there (8192^2: 0.599 against 0.600 ms/step).
 bool use_two(const lb_params& p, const Geom& g2)
 {
-    if (p.storage != LB_F32) return false;
+    if (p.storage != LB_F32 && p.storage != LB_F16DEV) return false;
     if (p.steps_per_launch == 2) return true;
-    return p.steps_per_launch == 0 && g2.tile_y >= 16;
+    return p.storage == LB_F32 && p.steps_per_launch == 0 && g2.tile_y >= 16;
 }
 
 // Workspace layout, each region 256-byte aligned.

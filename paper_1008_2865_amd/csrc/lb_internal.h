@@ -67,7 +67,7 @@ inline int storage_bytes(int storage)
 hipError_t launch_step(int storage, int mode, const void* src, void* dst,
                        const Geom& g, const Coef& c, double* partials,
                        hipStream_t s);
-// Two plain steps in one launch (FP32 storage only).  g is the two-step
+// Two plain steps in one launch (ST_F32 and ST_F16DEV storage).  g is the two-step
 // geometry: tile_x lanes produce tile_x - 6 output columns, tiles_x =
 // ceil(nx / (tile_x - 6)), blocks = tiles_x * ceil(ny / tile_y).
 hipError_t launch_step2(int storage, const void* src, void* dst, const Geom& g, const Coef& c,

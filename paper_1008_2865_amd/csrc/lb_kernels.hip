@@ -50,12 +50,25 @@ struct PF32 {
     __device__ static void st(S* p, C v, C) { *p = v; }
 };
 // Half-precision deviation from the rest-state equilibrium w_i rho_ref.
+// Decoding is one rounding of off + h and encoding one rounding of v - off
+// followed by the conversion, in every kernel and at every call site: with
+// contraction allowed the compiler could fuse the product w_i * rho_ref
+// that forms the offset into the add, in some inlined copies and not in
+// others, and the same stored value would decode to neighbouring floats.
 struct PF16 {
     using S = _Float16;
     using C = float;
     static constexpr bool kDev = true;
-    __device__ static C ld(const S* p, C off) { return off + (C)(*p); }
-    __device__ static void st(S* p, C v, C off) { *p = (S)(v - off); }
+    __device__ static C ld(const S* p, C off)
+    {
+#pragma clang fp contract(off)
+        return off + (C)(*p);
+    }
+    __device__ static void st(S* p, C v, C off)
+    {
+#pragma clang fp contract(off)
+        *p = (S)(v - off);
+    }
 };
 
 // Counter-based hash of (site, step): 32 well-mixed bits (the murmur3
@@ -141,7 +154,9 @@ struct Offs {
     typename P::C o0, o1, o2;  // rest, axis, diagonal
     __device__ Offs(typename P::C rho_ref)
     {
+#pragma clang fp contract(off)
         using C = typename P::C;
+        // Each offset is the rounded product; no later add may absorb it.
         if (P::kDev) {
             o0 = rho_ref * ((C)4 / (C)9);
             o1 = rho_ref * ((C)1 / (C)9);
@@ -165,6 +180,7 @@ __device__ __forceinline__ void store_site(typename P::S* const* pd, int at,
                                            const Offs<P>& o, uint32_t rnd)
 {
     if constexpr (P::kDev) {
+#pragma clang fp contract(off)
         float resid = q[0] - o.o0;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
@@ -629,8 +645,8 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
 }
 
 // ---------------------------------------------------------------------------
-// Two time steps per launch (temporal blocking) for plain single-precision
-// steps.  A tile of NT lanes produces NT - 6 output columns x0 .. x0+W-1 of
+// Two time steps per launch (temporal blocking) for plain steps of the
+// single-precision and half storages.  A tile of NT lanes produces NT - 6 output columns x0 .. x0+W-1 of
 // step t+2 for tile_y rows.  Level 1 is the one-step row walk above on the
 // NT columns x0-3 .. x0+NT-4 and on rows -3 .. nrows+2 of the tile (walk
 // order); its post-collision rows go to a 4-row LDS ring instead of memory.
@@ -649,7 +665,6 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
 {
     using S = typename P::S;
     using C = typename P::C;
-    static_assert(!P::kDev, "two-step launches store their first step in the arithmetic type");
     constexpr int W = NT - 6;           // output columns of the tile
     constexpr int LW = NT + 4;          // psi rings: lanes plus 2 columns each side
     constexpr int kWaves = NT / 64;
@@ -657,7 +672,9 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
     constexpr int RS = 6, RS2 = 6, NF = 4;
     __shared__ C ring[RS][LW];          // psi at t, level-1 rows p-2 .. p+3
     __shared__ C ring2[RS2][LW];        // psi at t+1, rows p-7 .. p-2
-    __shared__ C fs[NF][9][NT];         // post-collision populations of step t+1
+    // Post-collision populations of step t+1, in the storage type and
+    // rounded exactly as a one-step launch stores them.
+    __shared__ S fs[NF][9][NT];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -770,7 +787,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
                 // form values no output uses).
                 const int rr = p - 2 - q_cy(i) * dir;
                 const int li = min(max(tid - q_cx(i), 0), NT - 1);
-                Fr[i] = fs[(rr + 4) & 3][i][li];
+                Fr[i] = P::ld(&fs[(rr + 4) & 3][i][li], o.of(i));
             }
             ring2[(p - 2 + 12) % RS2][tid + 2] = psi_of(density(Fr), k2);
         }
@@ -786,8 +803,11 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
                                 ring[slot(2)], tid + 2);
             C q[9];
             site_collide<false>(Bf[J % 4], st, k, q, (C*)nullptr);
+            S* lp[9];
 #pragma unroll
-            for (int i = 0; i < 9; ++i) fs[(p + 4) & 3][i][tid] = q[i];
+            for (int i = 0; i < 9; ++i) lp[i] = &fs[(p + 4) & 3][i][0];
+            const uint32_t rnd = P::kDev ? site_hash(xc, wrow(p), k.step) : 0u;
+            store_site<P>(lp, tid, q, o, rnd);
             anchor = q[0];
         }
 
@@ -823,7 +843,9 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             site_collide<false>(F2[J % 4], st2, k2, q2, (C*)nullptr);
             if (own2) {
                 const int yq = wrow(qr);
-                store_site<P>(pd, yq * g.pitch + (x0 + tid - 3), q2, o, 0u);
+                const int xq = x0 + tid - 3;
+                const uint32_t rnd = P::kDev ? site_hash(xq, yq, k2.step) : 0u;
+                store_site<P>(pd, yq * g.pitch + xq, q2, o, rnd);
             }
         }
     };
@@ -1119,14 +1141,23 @@ hipError_t batch_p(int mode, int tile_x, int rpi, const BatchLaunch& a, hipStrea
 
 }  // namespace
 
+template <class P>
+hipError_t step2_p(const void* src, void* dst, const Geom& g, const Coef& c, hipStream_t s)
+{
+    switch (g.tile_x) {
+    case 64: return step2_nt<P, 64>(src, dst, g, c, s);
+    case 128: return step2_nt<P, 128>(src, dst, g, c, s);
+    case 256: return step2_nt<P, 256>(src, dst, g, c, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_step2(int storage, const void* src, void* dst, const Geom& g, const Coef& c,
                         hipStream_t s)
 {
-    if (storage != ST_F32) return hipErrorInvalidValue;
-    switch (g.tile_x) {
-    case 64: return step2_nt<PF32, 64>(src, dst, g, c, s);
-    case 128: return step2_nt<PF32, 128>(src, dst, g, c, s);
-    case 256: return step2_nt<PF32, 256>(src, dst, g, c, s);
+    switch (storage) {
+    case ST_F32: return step2_p<PF32>(src, dst, g, c, s);
+    case ST_F16DEV: return step2_p<PF16>(src, dst, g, c, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,10 +1,13 @@
-"""GPU: two plain steps per launch (temporal blocking, FP32 storage).
+"""GPU: two plain steps per launch (temporal blocking, FP32 and half storage).
 
 The two-step kernel applies to every site the same force and collision as
 the one-step kernel, so its fields must be bit-identical to one step per
 launch, for every tile shape, lattice size (small lattices whose tiles wrap
 around them included) and chunking of the run; logging splits the pairs at
-log points and records the same trace.
+log points and records the same trace.  In half storage the first step's
+populations pass through LDS rounded exactly as they would be stored (the
+rest population stochastically, from the same site hash), so the half
+fields are bit-identical too.
 """
 import numpy as np
 import pytest
@@ -23,9 +26,9 @@ from paper_1008_2865_amd.sim import LBSim  # noqa: E402
 R01 = inputs.couplings(0.1)
 
 
-def run(rho0, steps, spl, chunks=None, **kw):
+def run(rho0, steps, spl, chunks=None, storage="f32", **kw):
     G1, G2 = R01
-    sim = LBSim(rho0, G1=G1, G2=G2, storage="f32", max_steps=steps, steps_per_launch=spl, **kw)
+    sim = LBSim(rho0, G1=G1, G2=G2, storage=storage, max_steps=steps, steps_per_launch=spl, **kw)
     for n in (chunks or [steps]):
         sim.step(n)
     state, trace = sim.get_state(), sim.trace()
@@ -43,19 +46,23 @@ def run(rho0, steps, spl, chunks=None, **kw):
     (257, 11, 256, 4),
     (64, 64, 128, 64),
 ])
-def test_two_steps_per_launch_bit_identical(nx, ny, tile_x, tile_y):
-    print(f"two-step {nx}x{ny} tile {tile_x}x{tile_y}", flush=True)
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_two_steps_per_launch_bit_identical(nx, ny, tile_x, tile_y, storage):
+    print(f"two-step {storage} {nx}x{ny} tile {tile_x}x{tile_y}", flush=True)
     rho0 = inputs.rho_noise(nx, ny, 5)
-    a, _ = run(rho0, 61, 1, tile_x=tile_x, tile_y=tile_y)
-    b, _ = run(rho0, 61, 2, tile_x=tile_x, tile_y=tile_y)
-    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    a, _ = run(rho0, 61, 1, storage=storage, tile_x=tile_x, tile_y=tile_y)
+    b, _ = run(rho0, 61, 2, storage=storage, tile_x=tile_x, tile_y=tile_y)
+    bits = np.uint32 if storage == "f32" else np.uint16
+    assert np.array_equal(a.view(bits), b.view(bits))
 
 
-def test_logging_and_chunks():
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
+def test_logging_and_chunks(storage):
     rho0 = inputs.rho_noise(96, 80, 7)
-    a, ta = run(rho0, 100, 1, log_every=7, tile_y=16)
-    b, tb = run(rho0, 100, 2, log_every=7, chunks=[3, 50, 1, 46], tile_y=16)
-    assert np.array_equal(a.view(np.uint32), b.view(np.uint32))
+    a, ta = run(rho0, 100, 1, storage=storage, log_every=7, tile_y=16)
+    b, tb = run(rho0, 100, 2, storage=storage, log_every=7, chunks=[3, 50, 1, 46], tile_y=16)
+    bits = np.uint32 if storage == "f32" else np.uint16
+    assert np.array_equal(a.view(bits), b.view(bits))
     assert ta.shape == tb.shape and np.array_equal(ta, tb)
 
 
@@ -66,3 +73,18 @@ def test_full_size_against_oracle():
     fo = O.step(O.init(rho0), 6, 1.0, 1.0, G1, G2)
     a, _ = run(rho0, 6, 2)
     assert float(np.max(np.abs(a.astype(np.float64) - fo))) <= 2e-6
+
+
+def test_half_storage_decodes_identically_everywhere():
+    # 512^2 x 61 steps: about 16M site updates, in which a single decode of a
+    # stored half that rounded differently in one code path (the first rows
+    # of a tile against the rows of the walk, one step per launch against
+    # the LDS ring of two) would almost surely flip at least one
+    # stochastically rounded rest population.
+    rho0 = inputs.rho_noise(512, 512, 11)
+    ref, _ = run(rho0, 61, 1, storage="f16dev", tile_x=256, tile_y=32)
+    for spl, tx, ty, tr in [(1, 64, 7, 2), (1, 128, 1, 1), (2, 128, 24, 0), (2, 64, 5, 0)]:
+        print(f"f16dev 512^2 steps/launch {spl} tile {tx}x{ty}x{tr}", flush=True)
+        kw = dict(tile_x=tx, tile_y=ty) | ({"tile_rows": tr} if tr else {})
+        s, _ = run(rho0, 61, spl, storage="f16dev", **kw)
+        assert np.array_equal(s.view(np.uint16), ref.view(np.uint16))

@@ -185,23 +185,26 @@ const char* lb_last_error(void);
 /* ---------------------------------------------------------------------------
  * Batches: many independent periodic lattices, each with its own size,
  * couplings and initial density, advanced together by one kernel launch
- * per time step (the step of every lattice is exactly the one lb_step
- * performs, so its fields are bit-identical to a lb_step run of the same
- * lattice and launch shape).
+ * per time step, or per two plain steps under the same rule as
+ * lb_params.steps_per_launch (the step of every lattice is exactly the one
+ * lb_step performs, so its fields are bit-identical to a lb_step run of the
+ * same lattice).
  * ------------------------------------------------------------------------ */
 typedef struct lb_batch lb_batch;
 
 /* Workspace bytes for `count` lattices with parameters ps[0..count-1], or 0
  * if they are invalid.  All lattices must share storage, tile_x, tile_rows,
- * log_every and trace_cap (after the library's defaults are applied);
- * sizes, tile_y, tau, rho0, G1, G2 and rho_ref may differ. */
+ * steps_per_launch, log_every and trace_cap (after the library's defaults
+ * are applied); sizes, tile_y, tau, rho0, G1, G2 and rho_ref may differ. */
 size_t lb_batch_workspace_bytes(const lb_params* ps, int32_t count);
 
 /* Create a batch at t = 0; lattice i starts at rest with density
  * rho_init[i] (ny_i * nx_i doubles, host or device memory per
  * inputs_on_device).  Workspace and stream rules are those of lb_init.
  * When the stream is not the null stream, runs of plain steps are captured
- * into HIP graphs (one per run length and buffer parity) and replayed. */
+ * into HIP graphs (one per run length and buffer parity) and replayed,
+ * except for LB_F16DEV batches, whose rounding is seeded by the time level
+ * a graph would freeze. */
 int lb_batch_init(lb_batch** out, const lb_params* ps, int32_t count,
                   void* workspace, size_t bytes, const double* const* rho_init,
                   int inputs_on_device, void* hip_stream);
@@ -214,8 +217,14 @@ int lb_batch_init(lb_batch** out, const lb_params* ps, int32_t count,
 int lb_batch_step(lb_batch* b, int64_t n);
 
 /* Turn graph capture of plain steps on or off (LB_ERR_INVALID to turn it
- * on for the null stream). */
+ * on for the null stream or for an LB_F16DEV batch). */
 int lb_batch_use_graphs(lb_batch* b, int enable);
+
+/* Launch shape of the batch's two-step launches: columns per workgroup
+ * (each produces tile_x - 6 output columns), rows per workgroup and
+ * workgroups per launch over all lattices; all three are 0 when the batch
+ * runs one step per launch.  Any output may be NULL. */
+int lb_batch_two_step_shape(lb_batch* b, int32_t* tile_x, int32_t* tile_y, int32_t* blocks);
 
 /* Context of lattice i, owned by the batch: lb_moments, lb_pseudo_energy,
  * lb_trace, lb_time and lb_get_state accept it; lb_step, lb_set_state and

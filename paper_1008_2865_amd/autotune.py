@@ -50,8 +50,9 @@ def time_shape(nx, ny, storage, tile_x, tile_y, tile_rows, steps=100, warmup=20)
     from .sim import LBSim
 
     G1, G2 = inputs.couplings(0.1)
+    # One step per launch: the shape tuned here is that of the one-step kernel.
     sim = LBSim(inputs.rho_noise(nx, ny, 1), G1=G1, G2=G2, storage=storage, tile_x=tile_x,
-                tile_y=tile_y, tile_rows=tile_rows)
+                tile_y=tile_y, tile_rows=tile_rows, steps_per_launch=1)
     sim.step(warmup)
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
@@ -87,9 +88,10 @@ def tune(nx, ny, storage="f32", candidates=None, refresh=False, steps=100):
 
 def tune_batch(lattices, storage="f32", tile_x=None, tile_ys=(8, 16, 32, 64), tile_rows=(1, 2),
                refresh=False, steps=40):
-    """Shared (tile_x, tile_rows, tile_y) for a batch, timed on the whole
-    batch (one launch covers every lattice, so the batch's own parallelism,
-    not a single lattice's, decides the best tile height).  ``lattices``
+    """Shared (tile_x, tile_rows, tile_y) of the one-step kernel for a batch,
+    timed on the whole batch at one step per launch (one launch covers every
+    lattice, so the batch's own parallelism, not a single lattice's, decides
+    the best tile height).  ``lattices``
     are LBBatch lattice dicts; tile_x defaults to the widest strip every
     lattice fills."""
     import hashlib
@@ -114,7 +116,7 @@ def tune_batch(lattices, storage="f32", tile_x=None, tile_ys=(8, 16, 32, 64), ti
             continue
         for ty in tile_ys:
             lats = [dict(L, tile_y=min(ty, sh[0])) for L, sh in zip(lattices, shapes)]
-            batch = LBBatch(lats, storage=storage, tile_x=tile_x, tile_rows=tr)
+            batch = LBBatch(lats, storage=storage, tile_x=tile_x, tile_rows=tr, steps_per_launch=1)
             batch.step(10)
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)

@@ -71,6 +71,7 @@ SIGNATURES = {
                                      ctypes.POINTER(_vp), ctypes.c_int, _vp]),
     "lb_batch_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "lb_batch_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
+    "lb_batch_two_step_shape": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
     "lb_batch_member": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]),
     "lb_batch_destroy": (ctypes.c_int, [_vp]),
     "lb_adj_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int64, ctypes.c_int32]),
@@ -235,6 +236,13 @@ def lb_batch_step(b, n):
 
 def lb_batch_use_graphs(b, enable):
     return _check(lib().lb_batch_use_graphs(b, int(bool(enable))))
+
+
+def lb_batch_two_step_shape(b):
+    """(tile_x, tile_y, blocks) of the batch's two-step launches, zeros if unused."""
+    tx, ty, nb = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().lb_batch_two_step_shape(b, ctypes.byref(tx), ctypes.byref(ty), ctypes.byref(nb)))
+    return tx.value, ty.value, nb.value
 
 
 def lb_batch_member(b, i):

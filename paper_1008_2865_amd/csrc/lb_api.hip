@@ -243,8 +243,11 @@ struct lb_batch {
     std::vector<lb_ctx*> members;
     lbk::BatchLattice* desc;   // device
     int32_t* tile_lattice;     // device
+    int32_t* tile_lattice2;    // device, two-step tiles (when two)
     double* partials;          // device, 4 per tile
-    int tiles;
+    int tiles, tiles2;
+    bool two;                  // plain steps run two per launch
+    int tile_x2, tile_y2;
     int storage, tile_x, rows_per_iter, min_tile_y;
     int device;
     hipStream_t stream;
@@ -678,11 +681,23 @@ int check_batch(lb_batch* b)
 // Workspace of a batch: descriptor table, tile -> lattice table, partials,
 // then one single-lattice workspace per member.
 struct BatchLayout {
-    size_t desc, tile_lattice, partials;
+    size_t desc, tile_lattice, tile_lattice2, partials;
     std::vector<size_t> member, member_bytes;
     size_t total;
-    int tiles;
+    int tiles, tiles2, tile_y2;
+    bool two;
+    std::vector<Geom> geom2;
 };
+
+// Two-step geometry of a batch member: 128-lane tiles and a tile height
+// shared by the batch.
+Geom batch_geom2(const lb_params& p, int tile_y2)
+{
+    lb_params q = p;
+    q.tile_x = 128;
+    q.tile_y = std::min(tile_y2, p.ny);
+    return make_geom2(q, make_geom(q));
+}
 
 int batch_layout(const lb_params* ps, int32_t count, BatchLayout* L)
 {
@@ -703,15 +718,44 @@ int batch_layout(const lb_params* ps, int32_t count, BatchLayout* L)
             return fail(LB_ERR_INVALID,
                         "lattice %d: storage, tile_x, tile_rows, log_every and trace_cap must "
                         "match lattice 0", i);
+        if (ps[i].steps_per_launch != ps[0].steps_per_launch)
+            return fail(LB_ERR_INVALID, "lattice %d: steps_per_launch must match lattice 0", i);
         if ((int64_t)L->tiles + g.blocks >= (int64_t(1) << 30))
             return fail(LB_ERR_INVALID, "too many tiles in the batch");
         L->tiles += g.blocks;
     }
+    // Two steps per launch, as for a single lattice: FP32 by default when
+    // the batch as a whole fills tiles of >= 16 rows (the tallest of 48, 32,
+    // 24, 16 rows giving >= 1400 workgroups), half storage when asked for.
+    const int spl = ps[0].steps_per_launch;
+    int tile_y2 = 0;
+    for (int r : {48, 32, 24, 16}) {
+        int64_t blocks = 0;
+        for (int32_t i = 0; i < count; ++i) blocks += batch_geom2(ps[i], r).blocks;
+        if (blocks >= 1400 && blocks < (int64_t(1) << 30)) {
+            tile_y2 = r;
+            break;
+        }
+    }
+    const int st = ps[0].storage;
+    L->two = (st == LB_F32 && (spl == 2 || (spl == 0 && tile_y2 >= 16))) ||
+             (st == LB_F16DEV && spl == 2);
+    if (L->two && tile_y2 == 0) tile_y2 = 8;
+    L->tile_y2 = L->two ? tile_y2 : 0;
+    L->tiles2 = 0;
+    L->geom2.assign(count, Geom{});
+    if (L->two)
+        for (int32_t i = 0; i < count; ++i) {
+            L->geom2[i] = batch_geom2(ps[i], tile_y2);
+            L->tiles2 += L->geom2[i].blocks;
+        }
     size_t off = 0;
     L->desc = off;
     off += align_up(sizeof(lbk::BatchLattice) * count);
     L->tile_lattice = off;
     off += align_up(sizeof(int32_t) * L->tiles);
+    L->tile_lattice2 = off;
+    off += align_up(sizeof(int32_t) * L->tiles2);
     L->partials = off;
     off += align_up(sizeof(double) * 4 * L->tiles);
     L->member.resize(count);
@@ -725,15 +769,43 @@ int batch_layout(const lb_params* ps, int32_t count, BatchLayout* L)
     return LB_OK;
 }
 
-hipError_t batch_launch(lb_batch* b, int mode, int parity)
+// One step of every lattice from buf[parity]; t is the step's time level
+// (it seeds the half storage's stochastic rounding).
+hipError_t batch_launch(lb_batch* b, int mode, int parity, int64_t t)
 {
     return lbk::launch_step_batch(b->storage, mode, b->tile_x, b->rows_per_iter, b->min_tile_y, b->desc,
-                                  b->tile_lattice, b->tiles, parity, (uint32_t)b->t, b->partials,
+                                  b->tile_lattice, b->tiles, parity, (uint32_t)t, b->partials,
                                   b->stream);
+}
+
+// Buffer flips of a run of n plain steps: one per launch.
+int batch_flips(const lb_batch* b, int64_t n)
+{
+    return (int)((b->two ? n / 2 + (n & 1) : n) & 1);
+}
+
+// n plain steps from buf[parity] at time t, launch by launch: pairs in the
+// two-step kernel when the batch runs them so, then any odd step.
+hipError_t batch_run(lb_batch* b, int64_t n, int parity, int64_t t)
+{
+    int64_t j = 0;
+    if (b->two)
+        for (; j + 1 < n; j += 2, parity ^= 1) {
+            hipError_t e = lbk::launch_step2_batch(b->storage, b->tile_x2, b->desc, b->tile_lattice2,
+                                                   b->tiles2, parity, (uint32_t)(t + j), b->stream);
+            if (e != hipSuccess) return e;
+        }
+    for (; j < n; ++j, parity ^= 1) {
+        hipError_t e = batch_launch(b, lbk::MODE_STEP, parity, t + j);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 // n plain steps starting from the current parity, as one replay of a
 // captured graph when the stream allows capture, else launch by launch.
+// A graph keeps the time levels it was captured with, so batches whose
+// rounding depends on them (half storage) never use graphs.
 hipError_t batch_plain(lb_batch* b, int64_t n)
 {
     if (b->use_graphs && n >= 2) {
@@ -744,9 +816,7 @@ hipError_t batch_plain(lb_batch* b, int64_t n)
             hipGraphExec_t exec = nullptr;
             hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                hipError_t le = hipSuccess;
-                for (int64_t j = 0; j < n && le == hipSuccess; ++j)
-                    le = batch_launch(b, lbk::MODE_STEP, b->parity ^ (int)(j & 1));
+                const hipError_t le = batch_run(b, n, b->parity, b->t);
                 e = hipStreamEndCapture(b->stream, &graph);
                 if (e == hipSuccess && le != hipSuccess) e = le;
             }
@@ -762,16 +832,12 @@ hipError_t batch_plain(lb_batch* b, int64_t n)
         }
         return hipGraphLaunch(it->second, b->stream);
     }
-    for (int64_t j = 0; j < n; ++j) {
-        hipError_t e = batch_launch(b, lbk::MODE_STEP, b->parity ^ (int)(j & 1));
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return batch_run(b, n, b->parity, b->t);
 }
 
 int batch_log(lb_batch* b, int mode)
 {
-    hipError_t e = batch_launch(b, mode, b->parity);
+    hipError_t e = batch_launch(b, mode, b->parity, b->t);
     if (!e)
         e = lbk::launch_final_batch(b->desc, (int)b->members.size(), b->partials, (double)b->t,
                                     b->trace_rows, b->stream);
@@ -821,8 +887,8 @@ int lb_batch_init(lb_batch** out, const lb_params* ps, int32_t count, void* work
     lb_batch* b = new lb_batch();
     b->stream = static_cast<hipStream_t>(hip_stream);
     std::vector<lbk::BatchLattice> desc(count);
-    std::vector<int32_t> tl(L.tiles);
-    int tile = 0;
+    std::vector<int32_t> tl(L.tiles), tl2(L.tiles2);
+    int tile = 0, tile2 = 0;
     for (int32_t i = 0; i < count; ++i) {
         lb_ctx* c = nullptr;
         rc = lb_init(&c, &ps[i], ws + L.member[i], L.member_bytes[i], rho_init[i], nullptr, nullptr,
@@ -849,12 +915,23 @@ int lb_batch_init(lb_batch** out, const lb_params* ps, int32_t count, void* work
         d.tile_begin = tile;
         for (int j = 0; j < c->g.blocks; ++j) tl[tile + j] = i;
         tile += c->g.blocks;
+        if (L.two) {
+            d.geom2 = L.geom2[i];
+            d.tile_begin2 = tile2;
+            for (int j = 0; j < d.geom2.blocks; ++j) tl2[tile2 + j] = i;
+            tile2 += d.geom2.blocks;
+        }
     }
     lb_ctx* c0 = b->members[0];
     b->desc = reinterpret_cast<lbk::BatchLattice*>(ws + L.desc);
     b->tile_lattice = reinterpret_cast<int32_t*>(ws + L.tile_lattice);
+    b->tile_lattice2 = reinterpret_cast<int32_t*>(ws + L.tile_lattice2);
     b->partials = reinterpret_cast<double*>(ws + L.partials);
     b->tiles = L.tiles;
+    b->tiles2 = L.tiles2;
+    b->two = L.two;
+    b->tile_x2 = 128;
+    b->tile_y2 = L.tile_y2;
     b->storage = ps[0].storage;
     b->tile_x = c0->g.tile_x;
     b->min_tile_y = c0->g.tile_y;
@@ -867,11 +944,14 @@ int lb_batch_init(lb_batch** out, const lb_params* ps, int32_t count, void* work
     b->trace_cap = ps[0].trace_cap;
     b->trace_rows = 0;
     b->last_logged = -1;
-    b->use_graphs = b->stream != nullptr;
+    b->use_graphs = b->stream != nullptr && b->storage != LB_F16DEV;
     hipError_t e = hipMemcpyAsync(b->desc, desc.data(), sizeof(lbk::BatchLattice) * count,
                                   hipMemcpyHostToDevice, b->stream);
     if (!e) e = hipMemcpyAsync(b->tile_lattice, tl.data(), sizeof(int32_t) * L.tiles,
                                hipMemcpyHostToDevice, b->stream);
+    if (!e && L.tiles2)
+        e = hipMemcpyAsync(b->tile_lattice2, tl2.data(), sizeof(int32_t) * L.tiles2,
+                           hipMemcpyHostToDevice, b->stream);
     if (!e) e = hipStreamSynchronize(b->stream);
     if (e) {
         for (lb_ctx* m : b->members) {
@@ -924,7 +1004,7 @@ int lb_batch_step(lb_batch* b, int64_t n)
         }
         hipError_t e = batch_plain(b, run);
         if (e) return hip_fail(e, "batched step launch");
-        b->parity ^= (int)(run & 1);
+        b->parity ^= batch_flips(b, run);
         b->t += run;
         done += run;
     }
@@ -940,7 +1020,20 @@ int lb_batch_use_graphs(lb_batch* b, int enable)
     if (rc) return rc;
     if (enable && !b->stream)
         return fail(LB_ERR_INVALID, "the null stream cannot be captured into a graph");
+    if (enable && b->storage == LB_F16DEV)
+        return fail(LB_ERR_INVALID, "half-storage batches seed their rounding with the time "
+                                    "level and cannot replay captured graphs");
     b->use_graphs = enable != 0;
+    return LB_OK;
+}
+
+int lb_batch_two_step_shape(lb_batch* b, int32_t* tile_x, int32_t* tile_y, int32_t* blocks)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (tile_x) *tile_x = b->two ? b->tile_x2 : 0;
+    if (tile_y) *tile_y = b->two ? b->tile_y2 : 0;
+    if (blocks) *blocks = b->two ? b->tiles2 : 0;
     return LB_OK;
 }
 

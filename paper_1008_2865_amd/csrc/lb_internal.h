@@ -50,12 +50,13 @@ struct Coef {
 // One lattice of a batch, as the batched kernels read it (device memory).
 struct BatchLattice {
     Geom geom;
+    Geom geom2;          // two-step geometry (used when the batch runs two steps per launch)
     Coef coef;
     void* buf[2];        // population buffers; the step reads buf[parity]
     double* trace;       // this lattice's trace rows
     double half_A1;      // (G1 + G2) / 2
     int32_t tile_begin;  // first logical tile of this lattice in the batch
-    int32_t pad;
+    int32_t tile_begin2; // first logical tile of this lattice in the two-step tile list
 };
 
 // Bytes of one stored population value.
@@ -72,6 +73,13 @@ hipError_t launch_step(int storage, int mode, const void* src, void* dst,
 // ceil(nx / (tile_x - 6)), blocks = tiles_x * ceil(ny / tile_y).
 hipError_t launch_step2(int storage, const void* src, void* dst, const Geom& g, const Coef& c,
                         hipStream_t s);
+// Two plain steps of every lattice of a batch in one launch: tiles logical
+// tiles of tile_x lanes, tile_lattice maps each to its lattice, whose geom2
+// gives the tile's place; the launch reads buf[parity] and writes
+// buf[parity ^ 1] of every lattice.
+hipError_t launch_step2_batch(int storage, int tile_x, const BatchLattice* desc,
+                              const int32_t* tile_lattice, int tiles, int parity, uint32_t step,
+                              hipStream_t s);
 hipError_t launch_final(const double* partials, int blocks, double t,
                         double half_A1, double* out_row, hipStream_t s);
 hipError_t launch_step_batch(int storage, int mode, int tile_x, int rows_per_iter, int min_tile_y,

@@ -894,6 +894,21 @@ k_step(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
 // geometry, coefficients and buffers sit in desc.  Every lattice's tile is
 // processed exactly as the single-lattice kernel processes it, so fields
 // are bit-identical to single-lattice runs with the same tile shape.
+template <class P, int NT>
+__global__ void __launch_bounds__(NT)
+k_step2_batch(const BatchLattice* __restrict__ desc, const int32_t* __restrict__ tile_lattice,
+              int parity, uint32_t step)
+{
+    using S = typename P::S;
+    const int gl = xcd_remap(blockIdx.x, gridDim.x);
+    const int lat = tile_lattice[gl];
+    const BatchLattice& d = desc[lat];
+    CoefT<typename P::C> k = convert<typename P::C>(d.coef);
+    k.step = step;
+    step2_tile<P, NT>(static_cast<const S*>(d.buf[parity]), static_cast<S*>(d.buf[parity ^ 1]),
+                      d.geom2, k, gl - d.tile_begin2);
+}
+
 template <class P, int NT, int MODE, int RPI, int LEAD>
 __global__ void __launch_bounds__(NT)
 k_step_batch(const BatchLattice* __restrict__ desc, const int32_t* __restrict__ tile_lattice,
@@ -1148,6 +1163,38 @@ hipError_t step2_p(const void* src, void* dst, const Geom& g, const Coef& c, hip
     case 64: return step2_nt<P, 64>(src, dst, g, c, s);
     case 128: return step2_nt<P, 128>(src, dst, g, c, s);
     case 256: return step2_nt<P, 256>(src, dst, g, c, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class P>
+hipError_t step2_batch_p(int tile_x, const BatchLattice* desc, const int32_t* tile_lattice,
+                         int tiles, int parity, uint32_t step, hipStream_t s)
+{
+    const dim3 grid(tiles);
+    switch (tile_x) {
+    case 64:
+        hipLaunchKernelGGL((k_step2_batch<P, 64>), grid, dim3(64), 0, s, desc, tile_lattice, parity, step);
+        break;
+    case 128:
+        hipLaunchKernelGGL((k_step2_batch<P, 128>), grid, dim3(128), 0, s, desc, tile_lattice, parity, step);
+        break;
+    case 256:
+        hipLaunchKernelGGL((k_step2_batch<P, 256>), grid, dim3(256), 0, s, desc, tile_lattice, parity, step);
+        break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step2_batch(int storage, int tile_x, const BatchLattice* desc,
+                              const int32_t* tile_lattice, int tiles, int parity, uint32_t step,
+                              hipStream_t s)
+{
+    if (tiles <= 0) return hipErrorInvalidValue;
+    switch (storage) {
+    case ST_F32: return step2_batch_p<PF32>(tile_x, desc, tile_lattice, tiles, parity, step, s);
+    case ST_F16DEV: return step2_batch_p<PF16>(tile_x, desc, tile_lattice, tiles, parity, step, s);
     default: return hipErrorInvalidValue;
     }
 }

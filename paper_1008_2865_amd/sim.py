@@ -155,13 +155,13 @@ class LBBatch:
 
     ``lattices`` is a list of dicts with keys rho_init (ny, nx) and G1, G2
     (optionally tau, rho0, tile_y, rho_ref).  Shared settings (storage,
-    tile_x, tile_rows, log_every, trace_cap) are keyword arguments.  Plain
-    steps are captured into HIP graphs when the current torch stream is not
-    the null stream.
+    tile_x, tile_rows, log_every, trace_cap, steps_per_launch) are keyword
+    arguments.  Plain steps are captured into HIP graphs when the current
+    torch stream is not the null stream (not for half storage).
     """
 
     def __init__(self, lattices, *, storage="f32", tile_x=0, tile_rows=0, log_every=0,
-                 trace_cap=None, max_steps=None, use_graphs=True):
+                 trace_cap=None, max_steps=None, use_graphs=True, steps_per_launch=0):
         import torch
 
         if not torch.cuda.is_available():
@@ -179,7 +179,8 @@ class LBBatch:
                 nx, ny, storage=st, tau=L.get("tau", 1.0), rho0=L.get("rho0", 1.0),
                 G1=L["G1"], G2=L["G2"], log_every=log_every, trace_cap=trace_cap,
                 tile_x=tile_x, tile_y=L.get("tile_y", 0), tile_rows=tile_rows,
-                rho_ref=L.get("rho_ref", float(rho.mean())) if st == B.LB_F16DEV else 0.0))
+                rho_ref=L.get("rho_ref", float(rho.mean())) if st == B.LB_F16DEV else 0.0,
+                steps_per_launch=steps_per_launch))
             rhos.append(rho)
             self.shapes.append((ny, nx))
         nbytes = B.lb_batch_workspace_bytes(self.params)
@@ -192,7 +193,7 @@ class LBBatch:
         self.b = B.lb_batch_init(self.params, self.workspace, nbytes, rhos,
                                  stream=self.stream.cuda_stream)
         if not use_graphs or self.stream.cuda_stream == 0:
-            if self.stream.cuda_stream != 0:
+            if self.stream.cuda_stream != 0 and st != B.LB_F16DEV:
                 B.lb_batch_use_graphs(self.b, False)
         self.members = [_Member(self, i, nx, ny, storage, trace_cap)
                         for i, (ny, nx) in enumerate(self.shapes)]
@@ -200,6 +201,10 @@ class LBBatch:
 
     def step(self, n=1):
         B.lb_batch_step(self.b, n)
+
+    def two_step_shape(self):
+        """(tile_x, tile_y, workgroups) of the two-step launches, zeros if unused."""
+        return B.lb_batch_two_step_shape(self.b)
 
     def __getitem__(self, i):
         return self.members[i]

@@ -35,15 +35,23 @@ def lattices(seed0=10):
 
 
 @pytest.mark.parametrize("use_graphs", [True, False])
-@pytest.mark.parametrize("storage,tile_rows", [("f32", 1), ("f32", 2), ("f64", 1)])
-def test_batch_matches_single_lattice_runs(use_graphs, storage, tile_rows):
+@pytest.mark.parametrize("storage,tile_rows,spl", [
+    ("f32", 1, 0), ("f32", 2, 0), ("f64", 1, 0),
+    ("f32", 1, 2),        # plain steps two per launch (k_step2_batch)
+    ("f16dev", 1, 0),     # rounding seeded by the time level of every step
+    ("f16dev", 1, 2)])
+def test_batch_matches_single_lattice_runs(use_graphs, storage, tile_rows, spl):
+    print(f"batch {storage} rows/stage {tile_rows} steps/launch {spl} graphs {use_graphs}",
+          flush=True)
     lats = lattices()
     chunks = [37, 50, 13, 40]
     total = sum(chunks)
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         batch = LBBatch(lats, storage=storage, tile_x=64, tile_rows=tile_rows, log_every=10,
-                        max_steps=total, use_graphs=use_graphs)
+                        max_steps=total, use_graphs=use_graphs, steps_per_launch=spl)
+        tx2, ty2, nb2 = batch.two_step_shape()
+        assert (tx2 > 0) == (spl == 2) and (nb2 > 0) == (spl == 2)
         for n in chunks:
             batch.step(n)
             torch.cuda.synchronize()  # eager work between graph replays
@@ -54,7 +62,7 @@ def test_batch_matches_single_lattice_runs(use_graphs, storage, tile_rows):
                            max_steps=total)
             single.step(total)
             a, b = batch[k].get_state(), single.get_state()
-            word = np.uint64 if storage == "f64" else np.uint32
+            word = {"f64": np.uint64, "f32": np.uint32, "f16dev": np.uint16}[storage]
             assert np.array_equal(a.view(word), b.view(word)), k
             ta, tb = batch[k].trace(), single.trace()
             assert ta.shape == tb.shape == (total // 10 + 1, 6), (ta.shape, tb.shape)
@@ -92,10 +100,11 @@ def test_batch_members_cannot_be_stepped_alone():
 
 
 def test_full_sweep_sampled_lattices_against_oracle():
-    """The 96-lattice sweep (36.8 M sites) in one launch per step, FP32,
-    128 x 32 tiles with two rows per stage (the tuned shape): after a few
-    steps the smallest, a middle and the largest lattice match the oracle
-    pointwise."""
+    """The 96-lattice sweep (36.8 M sites), FP32, in the launch
+    configuration the benchmark times: the logged step in 128 x 32 tiles with
+    two rows per stage (the tuned one-step shape), the plain steps two per
+    launch (the default at this size).  After a few steps the smallest, a
+    middle and the largest lattice match the oracle pointwise."""
     spec = inputs.batched_lattices()
     lats = []
     for d in spec:
@@ -105,6 +114,7 @@ def test_full_sweep_sampled_lattices_against_oracle():
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         batch = LBBatch(lats, storage="f32", tile_x=128, tile_rows=2, log_every=5, max_steps=5)
+        assert batch.two_step_shape()[0] == 128
         batch.step(5)
         order = sorted(range(len(spec)), key=lambda k: spec[k]["n"])
         for k in (order[0], order[len(order) // 2], order[-1]):

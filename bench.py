@@ -27,7 +27,8 @@ PEAK_HBM_GBPS = 8000.0
 BYTES_PER_LU = {"f64": 144, "f32": 72, "f16dev": 36}
 METRIC = "MLUPS and achieved HBM GB/s (two-belt D2Q9 step); adjoint/forward time ratio"
 TRAFFIC_FILES = [os.path.join(ROOT, "profiles", "k_step2_f32_2048_traffic.txt"),
-                 os.path.join(ROOT, "profiles", "k_step_f32_2048_traffic.txt")]
+                 os.path.join(ROOT, "profiles", "k_step_f32_2048_traffic.txt"),
+                 os.path.join(ROOT, "profiles", "k_step2_batch_96_f32_traffic.txt")]
 KERNEL_SRC = os.path.join(ROOT, "paper_1008_2865_amd", "csrc", "lb_kernels.hip")
 
 
@@ -389,6 +390,9 @@ def bench_batch(args):
     # log_every): per step, times the steps a launch advances.
     per_launch = 2 if two else 1
     avg = step_s / launches * per_launch
+    workload_key = (f"batch {len(lats)} lattices {sites} sites {args.storage} "
+                    + (f"two-step tile {tx2}x{ty2}" if two else f"tile {tx}x{ty}x{tr}"))
+    traffic = measured_traffic(workload_key)
     out = {
         "metric": METRIC, "value": round(value, 1), "unit": "MLUPS", "n_gpus": 1, "steps": K,
         "warmup": W, "ms_per_step": round(region_s * 1e3 / K, 6), "higher_is_better": True,
@@ -408,7 +412,9 @@ def bench_batch(args):
             "bound": "hbm", "achieved": round(per_launch * bpl * sites / avg / 1e9, 1),
             "peak": PEAK_HBM_GBPS, "unit": "GB/s",
             "frac": round(per_launch * bpl * sites / avg / 1e9 / PEAK_HBM_GBPS, 4),
-            "traffic": None,
+            "traffic": traffic,
+            "traffic_gbps": round(traffic / avg / 1e9, 1) if traffic else None,
+            "workload_key": workload_key,
             "kernel": ("k_step2_batch (all lattices, two steps per launch)" if two
                        else "k_step_batch (all lattices, one launch per step)"),
             "algorithmic_bytes_per_launch": per_launch * bpl * sites,

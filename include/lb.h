@@ -65,7 +65,8 @@ enum lb_status {
 
 typedef struct lb_params {
     int32_t nx, ny;      /* periodic lattice; each >= 5 so the +-2 links of the
-                            second belt never alias onto one site; (nx+192)*ny < 2^31 */
+                            second belt never alias onto one site; (nx+192)*ny < 2^31,
+                            ny <= 65535                                           */
     int32_t storage;     /* lb_storage                                           */
     int32_t log_every;   /* > 0: record the section V energies every log_every
                             steps into the trace; 0: no trace                    */

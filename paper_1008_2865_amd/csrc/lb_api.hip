@@ -96,6 +96,9 @@ int check_params(const lb_params* p)
     // 32-bit offsets.
     if (((int64_t)p->nx + 192) * p->ny >= (int64_t(1) << 31))
         return fail(LB_ERR_INVALID, "(nx + 192) * ny must be < 2^31");
+    // The moments, initialisation and state kernels put rows on the grid's
+    // second dimension.
+    if (p->ny > 65535) return fail(LB_ERR_INVALID, "ny must be <= 65535 (got %d)", p->ny);
     if (p->storage != LB_F64 && p->storage != LB_F32 && p->storage != LB_F16DEV)
         return fail(LB_ERR_INVALID, "unknown storage %d", p->storage);
     if (p->log_every < 0) return fail(LB_ERR_INVALID, "log_every must be >= 0");

@@ -52,7 +52,8 @@ def good(**kw):
 @pytest.mark.parametrize("field,value", [
     ("nx", 4), ("ny", 3), ("storage", 7), ("tau", 0.5), ("tau", float("nan")),
     ("rho0", 0.0), ("G1", float("inf")), ("log_every", -1), ("trace_cap", -2),
-    ("tile_x", 96), ("tile_y", -1), ("tile_y", 5000), ("tile_rows", 3), ("steps_per_launch", 3), ("steps_per_launch", -1)])
+    ("tile_x", 96), ("tile_y", -1), ("tile_y", 5000), ("tile_rows", 3), ("steps_per_launch", 3),
+    ("steps_per_launch", -1), ("ny", 65536)])
 def test_validation_rejects(field, value):
     p = good()
     setattr(p, field, value)

@@ -163,21 +163,58 @@ Geom make_geom(const lb_params& p)
 // tiles, a 2048^2 lattice wants enough tiles to fill the chip (measured on
 // MI355X, FP32, us/step: 2048^2 42.8 at 128 x 24 against 46.3 at 128 x 32
 // and 48.8 at 128 x 16; 4096^2 149.4 at 128 x 48).
+// Workgroups of the two-step kernel resident at once: 3 waves per SIMD (its
+// registers and LDS), i.e. 6 of 128 lanes or 3 of 256 lanes per CU, on the
+// 256 CUs of the MI355X.
+int64_t step2_slots(int tile_x) { return 256 * (tile_x == 256 ? 3 : 6); }
+
+// Two-step launch shape.  A workgroup walks its rows one after the other,
+// so while every tile is resident at once (one round), shorter tiles finish
+// sooner: the default takes the shortest tiles (128 lanes, else 256) that
+// all fit in one round, up to 48 rows; larger lattices take 256-lane tiles
+// of about 48 rows, a few rows shorter when that fills the last round.
+// Measured on MI355X (FP32, us/step; one step per launch in brackets):
+//   1200^2 128x8 18.0 (20.0);  1800^2 128x18 30.0, 128x24 33.3 (43.0);
+//   2048^2 128x23 41.4, 128x24 42.1 (61.2);  2500^2 128x48 66.2, 128x40
+//   66.7 (115.7);  3000^2 256x47 81.3, 256x48 83.0, 128x48 108.6 (151.9);
+//   4096^2 256x46 150.0, 256x48 151.0 (243.9);  8192^2 256x45 589.6,
+//   256x48 604.6, 128x48 658.4 (1037.9).
 Geom make_geom2(const lb_params& p, const Geom& g)
 {
     Geom g2 = g;
-    if (!p.tile_x) g2.tile_x = 128;
-    if (!p.tile_y) {
-        static const int kRows[] = {48, 32, 24, 16, 8};
-        const int tx = (p.nx + g2.tile_x - 7) / (g2.tile_x - 6);
-        g2.tile_y = 8;
-        for (int r : kRows)
-            if ((int64_t)tx * ((p.ny + r - 1) / r) >= 1400) {
-                g2.tile_y = r;
+    auto strips = [&](int tx) { return (int64_t)(p.nx + tx - 7) / (tx - 6); };
+    auto rows = [&](int ty) { return (int64_t)(p.ny + ty - 1) / ty; };
+    int tx = p.tile_x, ty = p.tile_y;
+    if (!tx || !ty) {
+        int one_x = 0, one_y = 0;
+        for (int c : {128, 256}) {
+            if (tx && tx != c) continue;
+            const int64_t per_strip = step2_slots(c) / strips(c);
+            if (per_strip < 1) continue;
+            const int64_t h = (p.ny + per_strip - 1) / per_strip;
+            if (h <= 48) {
+                one_x = c;
+                one_y = (int)h;
                 break;
             }
-        if (g2.tile_y > p.ny) g2.tile_y = p.ny;
+        }
+        if (one_x) {
+            if (!tx) tx = one_x;
+            if (!ty) ty = one_y;
+        } else {
+            if (!tx) tx = 256;
+            if (!ty) {
+                ty = 48;
+                const int64_t slots = step2_slots(tx);
+                const int64_t rounds = (strips(tx) * rows(48) + slots - 1) / slots;
+                const int64_t per_strip = rounds * slots / strips(tx);
+                const int fit = per_strip > 0 ? (int)((p.ny + per_strip - 1) / per_strip) : 48;
+                if (fit >= 44 && fit < 48) ty = fit;
+            }
+        }
     }
+    g2.tile_x = tx;
+    g2.tile_y = ty > p.ny ? p.ny : ty;
     const int w = g2.tile_x - 6;
     g2.tiles_x = (p.nx + w - 1) / w;
     g2.blocks = g2.tiles_x * ((p.ny + g2.tile_y - 1) / g2.tile_y);
@@ -187,7 +224,7 @@ Geom make_geom2(const lb_params& p, const Geom& g)
 
 // Whether plain steps run two per launch: FP32 or half storage when asked
 // for (steps_per_launch = 2); by default FP32 storage on lattices large
-// enough for tiles of 16 rows or more (below that the one-step kernel is as
+// enough for tiles of 8 rows or more (below that the one-step kernel is as
 // fast or faster: 1024^2 16.6 us/step either way, 512^2 11.7 against 7.7).
 // Half storage stays at one step per launch by default: its step moves half
 // the bytes and is bound by arithmetic, not memory, so the two-step kernel
@@ -196,7 +233,7 @@ bool use_two(const lb_params& p, const Geom& g2)
 {
     if (p.storage != LB_F32 && p.storage != LB_F16DEV) return false;
     if (p.steps_per_launch == 2) return true;
-    return p.storage == LB_F32 && p.steps_per_launch == 0 && g2.tile_y >= 16;
+    return p.storage == LB_F32 && p.steps_per_launch == 0 && g2.tile_y >= 8;
 }
 
 // Workspace layout, each region 256-byte aligned.

@@ -205,3 +205,17 @@ def test_structure_factor_host_side():
 ])
 def test_default_launch_shape(n, shape):
     assert B.lb_launch_shape(B.make_params(n, n)) == shape
+
+
+@pytest.mark.parametrize("n,storage,spl,shape", [
+    (1024, P.LB_F32, 0, (0, 0, 0)),          # tiles under 16 rows: one step per launch
+    (2048, P.LB_F32, 0, (128, 23, 1530)),    # one round of resident 128-lane tiles
+    (4096, P.LB_F32, 0, (256, 46, 1530)),    # two rounds of 256-lane tiles
+    (8192, P.LB_F32, 0, (256, 45, 6039)),
+    (2048, P.LB_F32, 1, (0, 0, 0)),
+    (8192, P.LB_F16DEV, 0, (0, 0, 0)),       # half storage: opt-in only
+    (8192, P.LB_F16DEV, 2, (256, 45, 6039)),
+    (2048, P.LB_F64, 2, (0, 0, 0))])         # no double-precision two-step kernel
+def test_two_step_default_shape(n, storage, spl, shape):
+    p = good(nx=n, ny=n, storage=storage, steps_per_launch=spl, rho_ref=0.7)
+    assert B.lb_two_step_shape(p) == shape

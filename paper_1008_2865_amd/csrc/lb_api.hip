@@ -157,12 +157,8 @@ Geom make_geom(const lb_params& p)
 
 // Geometry of the two-step launches: tiles of tile_x lanes that produce
 // tile_x - 6 columns (the first step also covers 3 columns each side).
-// Explicit tile_x / tile_y apply to both kernels; the library's choice is
-// 128 lanes and the tallest of 48, 32, 24, 16, 8 rows that still gives
-// 1400 workgroups: the first step's 7 extra rows per tile favour tall
-// tiles, a 2048^2 lattice wants enough tiles to fill the chip (measured on
-// MI355X, FP32, us/step: 2048^2 42.8 at 128 x 24 against 46.3 at 128 x 32
-// and 48.8 at 128 x 16; 4096^2 149.4 at 128 x 48).
+// Explicit tile_x / tile_y apply to both kernels; the library's choice
+// follows.
 // Workgroups of the two-step kernel resident at once: 3 waves per SIMD (its
 // registers and LDS), i.e. 6 of 128 lanes or 3 of 256 lanes per CU, on the
 // 256 CUs of the MI355X.
@@ -764,9 +760,10 @@ int batch_layout(const lb_params* ps, int32_t count, BatchLayout* L)
             return fail(LB_ERR_INVALID, "too many tiles in the batch");
         L->tiles += g.blocks;
     }
-    // Two steps per launch, as for a single lattice: FP32 by default when
-    // the batch as a whole fills tiles of >= 16 rows (the tallest of 48, 32,
-    // 24, 16 rows giving >= 1400 workgroups), half storage when asked for.
+    // Two steps per launch: FP32 by default when the batch as a whole fills
+    // tiles of >= 16 rows (the tallest of 48, 32, 24, 16 rows giving >= 1400
+    // workgroups of 128 lanes; the lattices of a batch are narrow, so the
+    // tiles stay 128 lanes wide), half storage when asked for.
     const int spl = ps[0].steps_per_launch;
     int tile_y2 = 0;
     for (int r : {48, 32, 24, 16}) {

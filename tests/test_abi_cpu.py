@@ -147,9 +147,19 @@ def test_batch_rejects_mismatched_settings():
     for bad in ([B.make_params(64, 64, tile_x=64), B.make_params(64, 64, tile_x=128)],
                 [B.make_params(64, 64, tile_x=64), B.make_params(64, 64, tile_x=64, log_every=3)],
                 [B.make_params(64, 64, tile_x=64), B.make_params(64, 64, tile_x=64, storage=P.LB_F64)],
-                [B.make_params(64, 64, tile_x=64), B.make_params(4, 64, tile_x=64)]):
+                [B.make_params(64, 64, tile_x=64), B.make_params(4, 64, tile_x=64)],
+                [B.make_params(64, 64, tile_x=64), B.make_params(64, 64, tile_x=64,
+                                                                 steps_per_launch=2)]):
         assert B.lb_batch_workspace_bytes(bad) == 0
         assert P.lb_last_error()
+    # Two steps per launch add a second tile list to the workspace.
+    two = [B.make_params(64, 64, tile_x=64, steps_per_launch=2) for _ in range(2)]
+    one = [B.make_params(64, 64, tile_x=64, steps_per_launch=1) for _ in range(2)]
+    assert B.lb_batch_workspace_bytes(two) > B.lb_batch_workspace_bytes(one)
+    for fn in (B.lb_batch_two_step_shape, B.lb_batch_step):
+        with pytest.raises(B.LBError) as e:
+            fn(0x1234560) if fn is B.lb_batch_two_step_shape else fn(0x1234560, 1)
+        assert e.value.code == B.LB_ERR_STATE
 
 
 def test_adjoint_host_validation():

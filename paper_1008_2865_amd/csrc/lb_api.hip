@@ -945,6 +945,7 @@ int lb_batch_init(lb_batch** out, const lb_params* ps, int32_t count, void* work
         std::memset(&d, 0, sizeof d);
         d.geom = c->g;
         d.coef = c->coef;
+        lbk::coef_to_f32(c->coef, d.coef_f);
         d.buf[0] = c->buf[0];
         d.buf[1] = c->buf[1];
         d.trace = c->trace;

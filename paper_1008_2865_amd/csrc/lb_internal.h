@@ -57,7 +57,14 @@ struct BatchLattice {
     double half_A1;      // (G1 + G2) / 2
     int32_t tile_begin;  // first logical tile of this lattice in the batch
     int32_t tile_begin2; // first logical tile of this lattice in the two-step tile list
+    float coef_f[13];    // coef converted to single precision (coef_to_f32), so the
+                         // single-precision kernels read it without converting
+    int32_t pad;
 };
+
+// coef in single precision, exactly as the single-lattice launchers pass it:
+// K1, K2, K4, K5, K8, KE0, tau, omega, sqrt_rho0, inv_rho0, rho_ref, 2 K4, 2 K8.
+void coef_to_f32(const Coef& c, float out[13]);
 
 // Bytes of one stored population value.
 inline int storage_bytes(int storage)

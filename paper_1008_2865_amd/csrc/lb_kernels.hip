@@ -903,8 +903,10 @@ k_step2_batch(const BatchLattice* __restrict__ desc, const int32_t* __restrict__
     const int gl = xcd_remap(blockIdx.x, gridDim.x);
     const int lat = tile_lattice[gl];
     const BatchLattice& d = desc[lat];
-    CoefT<typename P::C> k = convert<typename P::C>(d.coef);
-    k.step = step;
+    static_assert(sizeof(typename P::C) == 4, "two-step kernels compute in single precision");
+    const float* cf = d.coef_f;
+    const CoefT<float> k{cf[0], cf[1], cf[2],  cf[3],  cf[4],  cf[5], cf[6],
+                         cf[7], cf[8], cf[9], cf[10], cf[11], cf[12], step};
     step2_tile<P, NT>(static_cast<const S*>(d.buf[parity]), static_cast<S*>(d.buf[parity ^ 1]),
                       d.geom2, k, gl - d.tile_begin2);
 }
@@ -1324,6 +1326,14 @@ hipError_t launch_get_state(int storage, const void* src, void* dense, const Geo
 hipError_t launch_set_state(int storage, const void* dense, void* dst, const Geom& g, hipStream_t s)
 {
     return state_copy<false>(storage, dense, dst, g, s);
+}
+
+void coef_to_f32(const Coef& c, float out[13])
+{
+    const CoefT<float> k = convert<float>(c);
+    const float v[13] = {k.K1, k.K2, k.K4, k.K5, k.K8, k.KE0, k.tau, k.omega,
+                         k.sqrt_rho0, k.inv_rho0, k.rho_ref, k.K4x2, k.K8x2};
+    for (int i = 0; i < 13; ++i) out[i] = v[i];
 }
 
 }  // namespace lbk

@@ -228,7 +228,7 @@ class AbiLattice:
     """One lattice driven through the oracle's lb_* entry points."""
 
     def __init__(self, rho_init, *, G1, G2, tau=1.0, rho0=1.0, log_every=0, trace_cap=0,
-                 precision="f64"):
+                 precision="f64", ux_init=None, uy_init=None):
         self.L = abi(precision)
         self.precision = precision
         rho = np.ascontiguousarray(rho_init, dtype=np.float64)
@@ -240,8 +240,10 @@ class AbiLattice:
             raise ValueError(self.L.lb_last_error().decode())
         self.ws = np.zeros(nbytes, np.uint8)
         self.ctx = _vp()
+        u = [None if a is None else np.ascontiguousarray(a, dtype=np.float64) for a in (ux_init, uy_init)]
         self._ok(self.L.lb_init(ctypes.byref(self.ctx), ctypes.byref(self.p), self.ws.ctypes.data,
-                                nbytes, rho.ctypes.data, None, None, 0, None))
+                                nbytes, rho.ctypes.data, *[None if a is None else a.ctypes.data for a in u],
+                                0, None))
         self.trace_cap = trace_cap
 
     def _ok(self, rc):

@@ -18,6 +18,9 @@ import oracle as O
 from paper_1008_2865_amd import inputs
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+# D2Q9 velocities in the interface's population order (section II).
+QX = np.array([0, 1, 0, -1, 0, 1, -1, -1, 1])
+QY = np.array([0, 0, 1, 0, -1, 1, 1, -1, -1])
 
 
 def core_symbols():
@@ -49,8 +52,30 @@ def test_call_sequence_equals_the_oracle_run():
     assert np.array_equal(lat.get_state(), f)
     rho, ux, uy = lat.moments()
     assert np.array_equal(rho, f.sum(axis=0))
+    # Reported velocity u = (sum_i c_i f_i) / rho of the state (section II
+    # moment definitions), with the D2Q9 velocities listed here.
+    state = lat.get_state()
+    jx, jy = np.tensordot(QX, state, axes=1), np.tensordot(QY, state, axes=1)
+    assert np.max(np.abs(ux - jx / rho)) <= 1e-14 * np.max(np.abs(ux))
+    assert np.max(np.abs(uy - jy / rho)) <= 1e-14 * np.max(np.abs(uy))
+    assert np.max(np.abs(ux)) > 1e-3 and np.max(np.abs(uy)) > 1e-3
     e = lat.pseudo_energy()
     assert e[0] == 1000 and np.array_equal(e[1:], tr_o[-1, 1:])
+    lat.close()
+
+
+def test_velocity_of_the_initial_equilibrium():
+    # lb_init with a velocity field starts from f^eq(rho, u); lb_moments at
+    # t = 0 must return that rho and u (first moments of the equilibrium).
+    rng = np.random.default_rng(21)
+    rho = inputs.rho_noise(18, 14, 3)
+    ux = rng.uniform(-0.05, 0.05, size=rho.shape)
+    uy = rng.uniform(-0.05, 0.05, size=rho.shape)
+    G1, G2 = inputs.couplings(0.1)
+    lat = O.AbiLattice(rho, G1=G1, G2=G2, ux_init=ux, uy_init=uy)
+    r, vx, vy = lat.moments()
+    assert np.max(np.abs(r - rho)) <= 2e-15
+    assert np.max(np.abs(vx - ux)) <= 1e-15 and np.max(np.abs(vy - uy)) <= 1e-15
     lat.close()
 
 

@@ -56,3 +56,30 @@ def test_gradients_match_finite_differences(tau, r):
     e[4, 7] = 1.0
     fde = (Lof(rho0 + h * e, G1, G2) - Lof(rho0 - h * e, G1, G2)) / (2 * h)
     assert abs(fde - drho[4, 7]) <= 1e-5 * abs(fde) + 1e-9
+
+
+@pytest.mark.parametrize("l,m", [(1, 0), (3, 2), (0, 4)])
+def test_interface_area_closed_form(l, m):
+    # Central differences are exact on a cosine.  For
+    # rho = a + b cos(kx x) + c cos(ky y), kx = 2 pi l / nx, ky = 2 pi m / ny:
+    # D_x rho = -b sin(kx) sin(kx x), D_y rho = -c sin(ky) sin(ky y), so
+    # A = sum_x sqrt(b^2 sin^2(kx) sin^2(kx x) + c^2 sin^2(ky) sin^2(ky y) + eps^2).
+    # A one-sided difference or a dropped factor 1/2 fails this.
+    nx, ny, a, b, c, eps = 24, 20, 0.7, 0.3, 0.2, 1e-3
+    kx, ky = 2 * np.pi * l / nx, 2 * np.pi * m / ny
+    y, x = np.mgrid[0:ny, 0:nx]
+    rho = a + b * np.cos(kx * x) + c * np.cos(ky * y)
+    dx = b * np.sin(kx) * np.sin(kx * x)
+    dy = c * np.sin(ky) * np.sin(ky * y)
+    A_ref = np.sqrt(dx * dx + dy * dy + eps * eps).sum()
+    f = torch.zeros((9, ny, nx), dtype=torch.float64)
+    f[0] = torch.tensor(rho)          # the measure reads the density only
+    area = float(A.interface_area(f, eps))
+    assert abs(area - A_ref) <= 1e-13 * A_ref
+
+
+def test_interface_area_of_a_uniform_field():
+    nx, ny, eps = 12, 9, 1e-6
+    f = torch.zeros((9, ny, nx), dtype=torch.float64)
+    f[:] = 0.7 / 9
+    assert abs(float(A.interface_area(f, eps)) - nx * ny * eps) <= 1e-12 * nx * ny * eps

@@ -111,6 +111,32 @@ def test_equilibrium_moments_textbook():
     assert np.allclose(pxy, rho * ux * uy, rtol=0, atol=1e-15)
 
 
+def test_oracle_moments_follow_the_definitions():
+    # Section II: rho = sum_i f_i and rho u = sum_i c_i f_i.  The oracle's own
+    # moments routine (its reported velocity is j / rho of it) must return
+    # (rho, rho u) for the equilibrium of a given (rho, u), the textbook first
+    # moment, and, for a field holding one population at a time, the
+    # momentum f c_i along the velocity that population streams with.
+    rng = np.random.default_rng(13)
+    rho = rng.uniform(0.1, 2.0, size=(7, 9))
+    ux = rng.uniform(-0.1, 0.1, size=(7, 9))
+    uy = rng.uniform(-0.1, 0.1, size=(7, 9))
+    r, jx, jy = O.moments(O.init(rho, ux, uy))
+    assert np.max(np.abs(r - rho)) <= 1e-15 * 2
+    assert np.max(np.abs(jx - rho * ux)) <= 1e-15
+    assert np.max(np.abs(jy - rho * uy)) <= 1e-15
+    for i in range(9):
+        f = np.zeros((9, 7, 9))
+        f[i] = rng.uniform(0.1, 1.0, size=(7, 9))
+        moved = O.stream(f)[i]
+        shifts = [(dx, dy) for dx in (-1, 0, 1) for dy in (-1, 0, 1)
+                  if np.array_equal(moved, np.roll(f[i], shift=(dy, dx), axis=(0, 1)))]
+        assert shifts == [Q_C[i]]
+        r, jx, jy = O.moments(f)
+        assert np.array_equal(r, f[i])
+        assert np.array_equal(jx, Q_C[i][0] * f[i]) and np.array_equal(jy, Q_C[i][1] * f[i])
+
+
 @pytest.mark.parametrize("tau", [1.0, 0.8, 1.7])
 def test_collision_conserves_mass_and_adds_force(tau):
     # Velocity-shift forcing: the post-collision momentum is j + F at every

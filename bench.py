@@ -113,6 +113,68 @@ def cpu_baseline(n, G1, G2, seed, target_s, steps=None):
             "cpu_gbps_at_144_B_per_LU": round(n * n * steps / dt * 144 / 1e9, 2)}
 
 
+def log_point_cost(sim, le, moments, B, reps=3):
+    """Extra seconds of a log point (the logged step plus lb_moments) over
+    a plain step, on the library's stream: (logged step + moments + one
+    plain step) against two plain steps, the pairs placed where the library
+    runs them so."""
+    import torch
+
+    extra = []
+    for _ in range(reps):
+        sim.step(le - sim.t % le)      # to the next log point (not timed)
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a.record()
+        sim.step(2)                    # the logged step and one plain step
+        B.lb_moments(sim.ctx, *moments, on_device=True)
+        b.record()
+        sim.step(2)                    # two plain steps (one launch where paired)
+        c.record()
+        torch.cuda.synchronize()
+        extra.append((a.elapsed_time(b) - b.elapsed_time(c)) / 1e3)
+    return max(0.0, sorted(extra)[len(extra) // 2])
+
+
+def adjoint_ratio(n, T, every, storage, r, seed, reps):
+    """Wall time of the backward pass over the forward pass of the adjoint
+    workload: gradients of L = (E(T) - E*)^2 + beta A(T) with respect to
+    G1, G2 and the initial density, E* = 1.01 E(T) of the same run,
+    beta = 1/n^2, eps = 1e-6, a checkpoint every `every` steps."""
+    import torch
+
+    from paper_1008_2865_amd import inputs
+    from paper_1008_2865_amd.adjoint import DropletLoss
+
+    G1, G2 = inputs.couplings(r)
+    rho = inputs.rho_noise(n, n, seed)
+    dl = DropletLoss(n, n, T, E_target=0.0, beta=1.0 / n ** 2, eps=1e-6, storage=storage,
+                     checkpoint_every=every)
+    dl.E_target = 1.01 * dl.forward(rho, G1, G2)[1]
+    dl.backward()  # warm-up pass
+    torch.cuda.synchronize()
+    fw, bw = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        L, E, A, M = dl.forward(rho, G1, G2)
+        t1 = time.perf_counter()
+        dG1, dG2, drho = dl.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        fw.append(t1 - t0)
+        bw.append(t2 - t1)
+        log(f"bench: adjoint forward {fw[-1] * 1e3:.1f} ms, backward {bw[-1] * 1e3:.1f} ms")
+    dl.close()
+    f_s, b_s = min(fw), min(bw)
+    return {"ratio": round(b_s / f_s, 3), "forward_ms": round(f_s * 1e3, 3),
+            "backward_ms": round(b_s * 1e3, 3),
+            "forward_mlups": round(n * n * T / f_s / 1e6, 1),
+            "config": f"{n}x{n} periodic two-belt D2Q9, r={r}, seed {seed}, {storage}, T={T}, "
+                      f"checkpoint every {every}, L=(E(T)-1.01 E_ref)^2 + A(T)/{n}^2, "
+                      f"best of {reps} (forward: T steps + checkpoints + loss; backward: "
+                      f"recomputed segments, tape, adjoint steps, gradients)",
+            "loss": [L, E, A, M], "dG": [dG1, dG2], "drho_l2": float(torch.linalg.norm(drho))}
+
+
 def copy_bandwidth(nbytes, reps=10):
     """GB/s of torch's device copy of an nbytes buffer (read + write)."""
     import torch
@@ -157,6 +219,9 @@ def main():
                          "droplet functional at 512^2 (adjoint/forward time ratio); structure: "
                          "the structure factor S(k), shell average and kbar at 512^2 and 2048^2")
     ap.add_argument("--checkpoint-every", type=int, default=100)
+    ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
+                    help="single workload: skip the adjoint/forward ratio of the 512^2 adjoint "
+                         "workload that the line carries by default")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -187,7 +252,7 @@ def main():
     rho0 = inputs.rho_noise(n, n, args.seed)
     total = W + K
     sim = LBSim(rho0, G1=G1, G2=G2, storage=args.storage, log_every=le,
-                max_steps=total + 2 * le + 1, tile_x=args.tile_x, tile_y=args.tile_y,
+                max_steps=total + 5 * le + 1000, tile_x=args.tile_x, tile_y=args.tile_y,
                 tile_rows=args.tile_rows, steps_per_launch=args.steps_per_launch)
     tx, ty, tr, nb = sim.launch_shape()
     tx2, ty2, nb2 = B.lb_two_step_shape(sim.p)
@@ -221,6 +286,7 @@ def main():
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
+    t_start = sim.t
     w0 = time.perf_counter()
     e0.record()
     run(K, pairs)
@@ -235,6 +301,14 @@ def main():
     log(f"bench: region {region_s * 1e3:.2f} ms (host wall {wall * 1e3:.2f} ms), "
         f"step chunks {step_s * 1e3:.2f} ms over {launches} steps; "
         f"trace rows {len(trace)}, last E = {last_e}")
+    # Logging (the logged step and lb_moments, one in le steps) at its
+    # workload share: a timed region shorter than le steps may hold no log
+    # point, or one at a 1/K share instead of 1/le.  The extra time of a log
+    # point over two plain steps is measured on its own and the region is
+    # charged K/le of them in place of the ones it actually held.
+    logs_in_region = sum(1 for t in range(t_start, t_start + K) if le and t % le == 0)
+    log_cost = log_point_cost(sim, le, moments, B) if le else 0.0
+    region_amortised = region_s + ((K / le if le else 0) - logs_in_region) * log_cost
 
     # The dominant kernel on its own: plain steps between two log points
     # (two per launch where the library runs them so), timed with HIP events
@@ -263,7 +337,7 @@ def main():
 
     sites = n * n
     bpl = BYTES_PER_LU[args.storage]
-    value = sites * K / region_s / 1e6
+    value = sites * K / region_amortised / 1e6
     alg_bytes = bpl * sites * per_launch_steps
     achieved = alg_bytes / avg_launch / 1e9
     workload_key = (f"{n}x{n} {args.storage} r={args.r} "
@@ -279,7 +353,7 @@ def main():
         "n_gpus": 1,
         "steps": K,
         "warmup": W,
-        "ms_per_step": round(region_s * 1e3 / K, 6),
+        "ms_per_step": round(region_amortised * 1e3 / K, 6),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -288,7 +362,12 @@ def main():
         "config": {
             "workload": f"two-belt D2Q9 Shan-Chen, {n}x{n} periodic, {args.storage} SoA populations, "
                         f"A1=-4.9, G2/|G1|={args.r}, tau=1, rho0=1, rho=0.7(1+0.01U) seed {args.seed}, "
-                        f"moments + pseudo-energy every {le} steps",
+                        f"moments + pseudo-energy every {le} steps (timed region: {K} steps holding "
+                        f"{logs_in_region} log point(s), charged {K / le if le else 0:g} log points "
+                        f"of {log_cost * 1e6:.1f} us each)",
+            "timed_region_ms": round(region_s * 1e3, 4),
+            "log_points_in_region": logs_in_region,
+            "log_point_extra_us": round(log_cost * 1e6, 2),
             "nx": n, "ny": n, "storage": args.storage, "G1": G1, "G2": G2, "tau": 1.0,
             "log_every": le, "tile_x": tx, "tile_y": ty, "tile_rows": tr, "workgroups": nb,
             "steps_per_launch": per_launch_steps,
@@ -308,10 +387,14 @@ def main():
             "avg_launch_us": round(avg_launch * 1e6, 3),
             "launches_timed": launches_probe,
             "traffic_gbps": round(traffic / avg_launch / 1e9, 1) if traffic else None,
+            "traffic_frac_of_peak": round(traffic / avg_launch / 1e9 / PEAK_HBM_GBPS, 4) if traffic else None,
             "device_copy_gbps": round(copy_gbps, 1),
-            "frac_of_device_copy": round(achieved / copy_gbps, 4),
+            "traffic_frac_of_device_copy": round(traffic / avg_launch / 1e9 / copy_gbps, 4) if traffic else None,
         },
     }
+    if args.adjoint:
+        log("bench: adjoint/forward ratio at the adjoint workload ...")
+        out["adjoint"] = adjoint_ratio(n=512, T=3000, every=100, storage="f32", r=0.1, seed=1, reps=3)
     if args.cpu_seconds > 0 or args.cpu_steps:
         log("bench: timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(n, G1, G2, args.seed, args.cpu_seconds, args.cpu_steps)
@@ -453,47 +536,25 @@ def bench_adjoint(args):
     import torch
 
     from paper_1008_2865_amd import inputs
-    from paper_1008_2865_amd.adjoint import DropletLoss
 
     n = args.n if args.n != 2048 else 512
     T = args.steps if args.steps != 20000 else 3000
-    reps = 3
+    log(f"bench: adjoint {n}x{n} {args.storage}, T {T}, checkpoint every {args.checkpoint_every}")
+    res = adjoint_ratio(n, T, args.checkpoint_every, args.storage, args.r, args.seed, reps=3)
+    f_s, b_s = res["forward_ms"] / 1e3, res["backward_ms"] / 1e3
+    L, E, A, M = res["loss"]
     G1, G2 = inputs.couplings(args.r)
     rho = inputs.rho_noise(n, n, args.seed)
-    dl = DropletLoss(n, n, T, E_target=0.0, beta=1.0 / n ** 2, eps=1e-6, storage=args.storage,
-                     checkpoint_every=args.checkpoint_every, tile_x=args.tile_x,
-                     tile_y=args.tile_y, tile_rows=args.tile_rows)
-    log(f"bench: adjoint {n}x{n} {args.storage}, T {T}, checkpoint every {args.checkpoint_every}")
-    dl.E_target = 1.01 * dl.forward(rho, G1, G2)[1]
-    dl.backward()  # warm-up pass
-    torch.cuda.synchronize()
-    fw, bw = [], []
-    for _ in range(reps):
-        t0 = time.perf_counter()
-        L, E, A, M = dl.forward(rho, G1, G2)
-        t1 = time.perf_counter()
-        dG1, dG2, drho = dl.backward()
-        torch.cuda.synchronize()
-        t2 = time.perf_counter()
-        fw.append(t1 - t0)
-        bw.append(t2 - t1)
-        log(f"bench: forward {fw[-1] * 1e3:.1f} ms, backward {bw[-1] * 1e3:.1f} ms")
-    dl.close()
-    f_s, b_s = min(fw), min(bw)
     out = {
         "metric": "adjoint/forward wall-time ratio (droplet functional gradients)",
-        "value": round(b_s / f_s, 3), "unit": "x", "n_gpus": 1, "steps": T, "warmup": 1,
+        "value": res["ratio"], "unit": "x", "n_gpus": 1, "steps": T, "warmup": 1,
         "ms_per_step": round((f_s + b_s) * 1e3 / T, 6), "higher_is_better": False,
         "scaling": "weak", "vs_baseline": None, "dtype": args.storage, "data": "synthetic",
-        "config": {
-            "workload": f"adjoint of a {n}x{n} periodic two-belt D2Q9 run, r={args.r}, seed "
-                        f"{args.seed}, {args.storage}, T={T}, checkpoint every "
-                        f"{args.checkpoint_every}, L=(E(T)-1.01 E_ref)^2 + A(T)/{n}^2",
-        },
-        "forward_ms": round(f_s * 1e3, 3), "backward_ms": round(b_s * 1e3, 3),
-        "forward_mlups": round(n * n * T / f_s / 1e6, 1),
+        "config": {"workload": "adjoint of a " + res["config"]},
+        "forward_ms": res["forward_ms"], "backward_ms": res["backward_ms"],
+        "forward_mlups": res["forward_mlups"],
         "gradient_mlups": round(n * n * T / (f_s + b_s) / 1e6, 1),
-        "loss": [L, E, A, M], "dG": [dG1, dG2], "drho_l2": float(torch.linalg.norm(drho)),
+        "loss": res["loss"], "dG": res["dG"], "drho_l2": res["drho_l2"],
     }
     if args.cpu_seconds > 0 or args.cpu_steps:
         log("bench: timing the oracle gradient on a bounded sample ...")

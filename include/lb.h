@@ -22,8 +22,12 @@
  *   - Every function returns LB_OK (0) on success and a negative lb_status
  *     on failure; lb_last_error() then holds a message (per thread).
  *     Arguments are checked on the host before anything is launched, and a
- *     call that fails leaves the context unchanged.  Nothing is thrown
- *     across this boundary.
+ *     call that fails leaves the context unchanged.  The one exception is a
+ *     HIP launch failure (LB_ERR_HIP) partway through a multi-step call
+ *     (lb_step, lb_batch_step): launches issued before the failure cannot
+ *     be withdrawn, so the context then holds the state they produce and
+ *     lb_time reports the time level reached.  Nothing is thrown across
+ *     this boundary.
  *   - Scalar fields are dense row-major double arrays of ny*nx values,
  *     site (x, y) at index y*nx + x.  Population arrays are dense
  *     [9][ny][nx] arrays of the storage type, population i in the D2Q9 order

@@ -122,8 +122,9 @@ int check_params(const lb_params* p)
     return LB_OK;
 }
 
-// Launch shape and layout.  Defaults: the widest column strip that the
-// lattice fills, 16 rows per workgroup.
+// Launch shape and layout.  Defaults: the widest column strip (256, 128 or
+// 64 columns) that the lattice fills, and the tallest tile of 32, 16, 8, 4
+// or 2 rows that still gives at least 512 workgroups.
 Geom make_geom(const lb_params& p)
 {
     Geom g;
@@ -542,10 +543,21 @@ int lb_step(lb_ctx* c, int64_t n)
             continue;
         }
         if (log) {
-            if ((rc = energy_row(c, lbk::MODE_STEP_ENERGY, src, dst, c->trace + c->trace_rows * 6)))
-                return rc;
-            c->last_logged = c->t;
+            // The logged step, then the reduction of its partials into the
+            // trace row.  If only the reduction fails to launch, the step
+            // itself was issued: the context follows it, without the row.
+            c->coef.step = (uint32_t)c->t;
+            hipError_t e = lbk::launch_step(c->p.storage, lbk::MODE_STEP_ENERGY, src, dst, c->g,
+                                            c->coef, c->partials, c->stream);
+            if (e) return hip_fail(e, "step kernel launch");
+            c->cur ^= 1;
+            ++c->t;
+            e = lbk::launch_final(c->partials, c->g.blocks, (double)(c->t - 1),
+                                  0.5 * (c->p.G1 + c->p.G2), c->trace + c->trace_rows * 6, c->stream);
+            if (e) return hip_fail(e, "final reduction launch");
+            c->last_logged = c->t - 1;
             ++c->trace_rows;
+            continue;
         } else {
             c->coef.step = (uint32_t)c->t;
             hipError_t e = lbk::launch_step(c->p.storage, lbk::MODE_STEP, src, dst, c->g, c->coef,
@@ -822,19 +834,23 @@ int batch_flips(const lb_batch* b, int64_t n)
 }
 
 // n plain steps from buf[parity] at time t, launch by launch: pairs in the
-// two-step kernel when the batch runs them so, then any odd step.
-hipError_t batch_run(lb_batch* b, int64_t n, int parity, int64_t t)
+// two-step kernel when the batch runs them so, then any odd step.  *done
+// counts the steps whose launch was issued (all n unless one fails).
+hipError_t batch_run(lb_batch* b, int64_t n, int parity, int64_t t, int64_t* done)
 {
     int64_t j = 0;
+    *done = 0;
     if (b->two)
         for (; j + 1 < n; j += 2, parity ^= 1) {
             hipError_t e = lbk::launch_step2_batch(b->storage, b->tile_x2, b->desc, b->tile_lattice2,
                                                    b->tiles2, parity, (uint32_t)(t + j), b->stream);
             if (e != hipSuccess) return e;
+            *done = j + 2;
         }
     for (; j < n; ++j, parity ^= 1) {
         hipError_t e = batch_launch(b, lbk::MODE_STEP, parity, t + j);
         if (e != hipSuccess) return e;
+        *done = j + 1;
     }
     return hipSuccess;
 }
@@ -842,9 +858,11 @@ hipError_t batch_run(lb_batch* b, int64_t n, int parity, int64_t t)
 // n plain steps starting from the current parity, as one replay of a
 // captured graph when the stream allows capture, else launch by launch.
 // A graph keeps the time levels it was captured with, so batches whose
-// rounding depends on them (half storage) never use graphs.
-hipError_t batch_plain(lb_batch* b, int64_t n)
+// rounding depends on them (half storage) never use graphs.  *done counts
+// the steps issued.
+hipError_t batch_plain(lb_batch* b, int64_t n, int64_t* done)
 {
+    *done = 0;
     if (b->use_graphs && n >= 2) {
         const auto key = std::make_pair(n, b->parity);
         auto it = b->graphs.find(key);
@@ -853,7 +871,8 @@ hipError_t batch_plain(lb_batch* b, int64_t n)
             hipGraphExec_t exec = nullptr;
             hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                const hipError_t le = batch_run(b, n, b->parity, b->t);
+                int64_t captured = 0;
+                const hipError_t le = batch_run(b, n, b->parity, b->t, &captured);
                 e = hipStreamEndCapture(b->stream, &graph);
                 if (e == hipSuccess && le != hipSuccess) e = le;
             }
@@ -863,13 +882,15 @@ hipError_t batch_plain(lb_batch* b, int64_t n)
                 // This stream cannot be captured: run launch by launch from now on.
                 (void)hipGetLastError();
                 b->use_graphs = false;
-                return batch_plain(b, n);
+                return batch_plain(b, n, done);
             }
             it = b->graphs.emplace(key, exec).first;
         }
-        return hipGraphLaunch(it->second, b->stream);
+        const hipError_t e = hipGraphLaunch(it->second, b->stream);
+        if (e == hipSuccess) *done = n;
+        return e;
     }
-    return batch_run(b, n, b->parity, b->t);
+    return batch_run(b, n, b->parity, b->t, done);
 }
 
 int batch_log(lb_batch* b, int mode)
@@ -881,6 +902,45 @@ int batch_log(lb_batch* b, int mode)
     if (e) return hip_fail(e, "batched energy launch");
     b->last_logged = b->t;
     ++b->trace_rows;
+    return LB_OK;
+}
+
+// n steps of the batch, logging where due; the batch's time level and
+// parity follow every launch that was issued.
+int batch_advance(lb_batch* b, int64_t n)
+{
+    const int64_t le = b->log_every;
+    int rc;
+    int64_t done = 0;
+    while (done < n) {
+        if (le > 0 && b->t % le == 0 && b->last_logged != b->t) {
+            hipError_t e = batch_launch(b, lbk::MODE_STEP_ENERGY, b->parity, b->t);
+            if (e) return hip_fail(e, "batched energy launch");
+            b->parity ^= 1;
+            ++b->t;
+            ++done;
+            e = lbk::launch_final_batch(b->desc, (int)b->members.size(), b->partials,
+                                        (double)(b->t - 1), b->trace_rows, b->stream);
+            if (e) return hip_fail(e, "batched energy reduction launch");
+            b->last_logged = b->t - 1;
+            ++b->trace_rows;
+            continue;
+        }
+        int64_t run = n - done;
+        if (le > 0) {
+            const int64_t next = (b->t / le + 1) * le;
+            if (next - b->t < run) run = next - b->t;
+        }
+        int64_t issued = 0;
+        hipError_t e = batch_plain(b, run, &issued);
+        // Launches issued: pairs first, then any odd step (as batch_run).
+        b->parity ^= batch_flips(b, issued);
+        b->t += issued;
+        done += issued;
+        if (e) return hip_fail(e, "batched step launch");
+    }
+    if (le > 0 && b->t % le == 0 && b->last_logged != b->t)
+        if ((rc = batch_log(b, lbk::MODE_ENERGY))) return rc;
     return LB_OK;
 }
 
@@ -1026,30 +1086,11 @@ int lb_batch_step(lb_batch* b, int64_t n)
                     (long long)b->trace_rows, (long long)need, (long long)b->trace_cap);
     DeviceGuard dg(b->device);
     if (dg.err) return hip_fail(dg.err, "select device");
-    int64_t done = 0;
-    while (done < n) {
-        if (le > 0 && b->t % le == 0 && b->last_logged != b->t) {
-            if ((rc = batch_log(b, lbk::MODE_STEP_ENERGY))) return rc;
-            b->parity ^= 1;
-            ++b->t;
-            ++done;
-            continue;
-        }
-        int64_t run = n - done;
-        if (le > 0) {
-            const int64_t next = (b->t / le + 1) * le;
-            if (next - b->t < run) run = next - b->t;
-        }
-        hipError_t e = batch_plain(b, run);
-        if (e) return hip_fail(e, "batched step launch");
-        b->parity ^= batch_flips(b, run);
-        b->t += run;
-        done += run;
-    }
-    if (le > 0 && b->t % le == 0 && b->last_logged != b->t)
-        if ((rc = batch_log(b, lbk::MODE_ENERGY))) return rc;
+    // On a launch failure the steps issued before it stand: the batch and
+    // its member contexts are left at the time level they reached.
+    rc = batch_advance(b, n);
     batch_sync_members(b);
-    return LB_OK;
+    return rc;
 }
 
 int lb_batch_use_graphs(lb_batch* b, int enable)

@@ -1,0 +1,57 @@
+"""Write the long-run energy traces that the GPU tests compare against.
+
+Runs only the CPU oracle (FP64, and its FP32 twin, which sizes the
+single-precision tolerance) on the 2048 x 2048 periodic two-belt workload
+(r = G2/|G1| = 0.1 at A1 = G1 + G2 = -4.9, tau = 1, rho0 = 1, initial
+rho = 0.7 (1 + 0.01 U(-1, 1)) with seed 1), 20000 steps, and records the
+section V observables {t, M, E_s, E_m, sum psi^2, E_bulk} of the
+pre-collision state at every 500 steps.  About 25 minutes on 6 threads:
+
+    OMP_NUM_THREADS=6 python tests/golden/make_long_trace.py
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import oracle as O  # noqa: E402
+from paper_1008_2865_amd import inputs  # noqa: E402
+
+N, STEPS, LOG, R, SEED = 2048, 20000, 500, 0.1, 1
+OUT = os.path.join(HERE, f"trace_{N}_r{R}_seed{SEED}_{STEPS}.txt")
+
+
+def trace(precision):
+    G1, G2 = inputs.couplings(R)
+    f = O.init(inputs.rho_noise(N, N, SEED), precision=precision)
+    rows, t0 = [], time.perf_counter()
+    for c in range(STEPS // LOG):
+        f, tr = O.run(f, LOG, 1.0, 1.0, G1, G2, LOG, precision=precision)
+        row = tr[0].copy()
+        row[0] = c * LOG                  # a chunk's trace counts time from its start
+        rows.append(row)
+        print(f"{precision}: t = {(c + 1) * LOG} ({time.perf_counter() - t0:.0f} s)", flush=True)
+    rows.append(np.concatenate([[STEPS], O.observables(f, 1.0, G1, G2, precision=precision)]))
+    return np.array(rows)
+
+
+def main():
+    f64 = trace("f64")
+    f32 = trace("f32")
+    with open(OUT, "w") as fh:
+        fh.write(f"# Section V observables of the {N}x{N} periodic two-belt workload, r = {R}\n")
+        fh.write(f"# (A1 = -4.9, tau = 1, rho0 = 1, rho = 0.7(1 + 0.01 U(-1,1)), seed {SEED}),\n")
+        fh.write(f"# every {LOG} steps to {STEPS}; written by make_long_trace.py from the oracle only.\n")
+        fh.write("# columns: precision t M E_s E_m sum_psi2 E_bulk (f64 = the oracle, f32 = its twin)\n")
+        for name, tr in (("f64", f64), ("f32", f32)):
+            for row in tr:
+                fh.write(name + " " + " ".join(repr(float(v)) for v in row) + "\n")
+    print("wrote", OUT)
+
+
+if __name__ == "__main__":
+    main()

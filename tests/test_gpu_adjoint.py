@@ -151,3 +151,51 @@ def test_f32_adjoint_against_f64_at_512(steps, tol_E, tol_G, tol_rho):
     assert close(grads["f32"][0], grads["f64"][0], tol_G)
     assert close(grads["f32"][1], grads["f64"][1], tol_G)
     assert rel <= tol_rho
+
+
+def test_adjoint_workload_full_length():
+    """The adjoint workload itself: 512^2, T = 3000, a checkpoint every 100
+    steps, E* = 1.01 E(T) of the FP64 run, beta = 1/512^2, eps = 1e-6.
+
+    The FP64 gradients are checked against central finite differences of
+    the FP64 loss (h = 1e-4, the workload's step): dL/dG1, dL/dG2 and the
+    derivative of L along a fixed random direction of the initial density.
+    The FP32 gradients are checked against the FP64 ones."""
+    n, T, K = 512, 3000, 100
+    G1, G2 = inputs.couplings(0.1)
+    rho = inputs.rho_noise(n, n, 1)
+    beta = 1.0 / n ** 2
+    probe = DropletLoss(n, n, T, E_target=0.0, beta=0.0, storage="f64", checkpoint_every=K)
+    Et = 1.01 * probe.forward(rho, G1, G2)[1]
+    probe.close()
+    res = {}
+    for st in ("f64", "f32"):
+        print(f"adjoint {st} {n}x{n} T={T} every={K}", flush=True)
+        dl = DropletLoss(n, n, T, E_target=Et, beta=beta, storage=st, checkpoint_every=K)
+        L = dl.forward(rho, G1, G2)[0]
+        dG1, dG2, drho = dl.backward()
+        res[st] = (L, dG1, dG2, drho.cpu().numpy())
+        dl.close()
+
+    dl = DropletLoss(n, n, T, E_target=Et, beta=beta, storage="f64", checkpoint_every=K)
+    h = 1e-4
+    v = np.random.default_rng(7).standard_normal((n, n)) * 0.7
+
+    def Lof(r_, g1, g2):
+        return dl.forward(r_, g1, g2)[0]
+
+    fd1 = (Lof(rho, G1 + h, G2) - Lof(rho, G1 - h, G2)) / (2 * h)
+    fd2 = (Lof(rho, G1, G2 + h) - Lof(rho, G1, G2 - h)) / (2 * h)
+    fdv = (Lof(rho + h * v, G1, G2) - Lof(rho - h * v, G1, G2)) / (2 * h)
+    dl.close()
+    L64, a1, a2, d64 = res["f64"]
+    av = float((d64 * v).sum())
+    L32, b1, b2, d32 = res["f32"]
+    rel = float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64))
+    print(f"C5 f64: L {L64:.9e} dG1 {a1:.9e} (FD {fd1:.9e}) dG2 {a2:.9e} (FD {fd2:.9e}) "
+          f"d/dv {av:.9e} (FD {fdv:.9e})", flush=True)
+    print(f"C5 f32: L {L32:.9e} dG1 {b1:.9e} dG2 {b2:.9e} drho rel L2 vs f64 {rel:.3e}", flush=True)
+    assert close(a1, fd1, 1e-3) and close(a2, fd2, 1e-3) and close(av, fdv, 1e-3)
+    assert close(L32, L64, 1e-2)
+    assert close(b1, a1, 0.1) and close(b2, a2, 0.1)
+    assert rel <= 1.0

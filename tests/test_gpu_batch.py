@@ -99,12 +99,12 @@ def test_batch_members_cannot_be_stepped_alone():
     batch.close()
 
 
-def test_full_sweep_sampled_lattices_against_oracle():
+def test_full_sweep_against_oracle():
     """The 96-lattice sweep (36.8 M sites), FP32, in the launch
     configuration the benchmark times: the logged step in 128 x 32 tiles with
     two rows per stage (the tuned one-step shape), the plain steps two per
-    launch (the default at this size).  After a few steps the smallest, a
-    middle and the largest lattice match the oracle pointwise."""
+    launch (the default at this size).  After a few steps every lattice
+    matches the oracle pointwise, and its energy row too."""
     spec = inputs.batched_lattices()
     lats = []
     for d in spec:
@@ -116,13 +116,17 @@ def test_full_sweep_sampled_lattices_against_oracle():
         batch = LBBatch(lats, storage="f32", tile_x=128, tile_rows=2, log_every=5, max_steps=5)
         assert batch.two_step_shape()[0] == 128
         batch.step(5)
-        order = sorted(range(len(spec)), key=lambda k: spec[k]["n"])
-        for k in (order[0], order[len(order) // 2], order[-1]):
-            L = lats[k]
+        worst_rho, worst_e = 0.0, 0.0
+        for k, L in enumerate(lats):
             fo = O.step(O.init(L["rho_init"]), 5, 1.0, 1.0, L["G1"], L["G2"])
             rho = batch[k].moments()[0]
-            assert float(np.max(np.abs(rho - fo.sum(axis=0)))) <= 2e-6, k
+            d = float(np.max(np.abs(rho - fo.sum(axis=0))))
             tr = batch[k].trace()
             eo = O.observables(fo, 1.0, L["G1"], L["G2"])
-            assert tr.shape == (2, 6) and np.all(np.abs(tr[1, 1:] - eo) <= 1e-5 * np.abs(eo)), k
+            de = float(np.max(np.abs(tr[1, 1:] - eo) / np.abs(eo)))
+            worst_rho, worst_e = max(worst_rho, d), max(worst_e, de)
+            assert d <= 2e-6, (k, spec[k], d)
+            assert tr.shape == (2, 6) and tr[1, 0] == 5 and de <= 1e-5, (k, spec[k], de)
+        print(f"96-lattice sweep after 5 steps: max|drho| {worst_rho:.3e}, "
+              f"max rel energy-row difference {worst_e:.3e}", flush=True)
         batch.close()

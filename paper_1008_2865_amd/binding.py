@@ -86,6 +86,7 @@ SIGNATURES = {
     "lb_sk_init": (ctypes.c_int, [ctypes.POINTER(_vp), ctypes.c_int32, _vp, ctypes.c_size_t, _vp]),
     "lb_sk_compute": (ctypes.c_int, [_vp, _vp, ctypes.c_int, _vp, _vp, ctypes.c_int32, _vp, _vp]),
     "lb_sk_destroy": (ctypes.c_int, [_vp]),
+    "lb_pseudo_energy_state": (ctypes.c_int, [_P, _vp, ctypes.c_double, _vp, _vp]),
 }
 
 _lib = None
@@ -313,3 +314,14 @@ def lb_sk_compute(s, rho, shell, counts, kbar_out=None, spectrum=None, on_device
 
 def lb_sk_destroy(s):
     return _check(lib().lb_sk_destroy(s))
+
+
+def lb_pseudo_energy_state(p, state, t, stream):
+    """{t, M, E_s, E_m, sum psi^2, E_bulk} of a dense [9][ny][nx] device
+    population array, without a context or workspace (numpy float64[6])."""
+    import numpy as np
+
+    out = np.empty(6, np.float64)
+    _check(lib().lb_pseudo_energy_state(ctypes.byref(p), _ptr(state), float(t), out.ctypes.data,
+                                        stream or None))
+    return out

@@ -13,6 +13,7 @@ LIB = os.path.join(HERE, "liblb.so")
 SOURCES = [os.path.join(HERE, "csrc", "lb_kernels.hip"),
            os.path.join(HERE, "csrc", "lb_adjoint.hip"),
            os.path.join(HERE, "csrc", "lb_structure.hip"),
+           os.path.join(HERE, "csrc", "lb_noalloc.hip"),
            os.path.join(HERE, "csrc", "lb_api.hip")]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

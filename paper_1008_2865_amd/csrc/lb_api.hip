@@ -697,6 +697,24 @@ int lb_set_state(lb_ctx* c, const void* src, int on_device, int64_t t)
     return LB_OK;
 }
 
+int lb_pseudo_energy_state(const lb_params* p, const void* state, double t, double out[6],
+                           void* hip_stream)
+{
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (!state) return fail(LB_ERR_INVALID, "state is NULL");
+    if (!out) return fail(LB_ERR_INVALID, "out is NULL");
+    if (!std::isfinite(t)) return fail(LB_ERR_INVALID, "t must be finite");
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess || ndev <= 0) return fail(LB_ERR_HIP, "no HIP device available");
+    e = lbk::noalloc_energy(p->storage, state, p->nx, p->ny, make_coef(*p), t, 0.5 * (p->G1 + p->G2),
+                            out, static_cast<hipStream_t>(hip_stream));
+    if (e) return hip_fail(e, "energy of a population array");
+    if (!rows_finite(out, 1)) return fail(LB_ERR_NONFINITE, "non-finite mass or energy");
+    return LB_OK;
+}
+
 int lb_destroy(lb_ctx* c)
 {
     {

@@ -105,6 +105,14 @@ hipError_t launch_get_state(int storage, const void* src, void* dense,
 hipError_t launch_set_state(int storage, const void* dense, void* dst,
                             const Geom& g, hipStream_t s);
 
+// Section V observables {t, M, E_s, E_m, sum psi^2, E_bulk} of a dense
+// [9][ny][nx] pre-collision population array of the given storage (device
+// memory) into out (host, 6 doubles), with every intermediate in the
+// library's static device scratch (lb_noalloc.hip): no allocation, and the
+// stream is synchronised before returning.
+hipError_t noalloc_energy(int storage, const void* state, int nx, int ny, const Coef& c, double t,
+                          double half_A1, double* out, hipStream_t s);
+
 // Adjoint kernels (lb_adjoint.hip).  Arithmetic is double when f64 != 0,
 // float otherwise; arrays are dense [component][ny][nx] of that type.
 struct AdjParams {

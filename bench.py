@@ -219,6 +219,8 @@ def main():
                          "droplet functional at 512^2 (adjoint/forward time ratio); structure: "
                          "the structure factor S(k), shell average and kbar at 512^2 and 2048^2")
     ap.add_argument("--checkpoint-every", type=int, default=100)
+    ap.add_argument("--tile-y2", type=int, default=0,
+                    help="batch: rows per workgroup of the two-step launches (0: tuned)")
     ap.add_argument("--no-adjoint", dest="adjoint", action="store_false",
                     help="single workload: skip the adjoint/forward ratio of the 512^2 adjoint "
                          "workload that the line carries by default")
@@ -428,8 +430,14 @@ def bench_batch(args):
         for L in lats:
             L["tile_y"] = ty
         batch = LBBatch(lats, storage=args.storage, tile_x=tx, tile_rows=tr, log_every=le,
-                        max_steps=W + K + le, steps_per_launch=args.steps_per_launch)
+                        max_steps=W + K + le + 1000, steps_per_launch=args.steps_per_launch)
         sites = batch.sites
+        if batch.two_step_shape()[0]:
+            # The two-step tile height, timed on this batch (or given).
+            if args.tile_y2:
+                batch.set_two_step_tile(args.tile_y2)
+            else:
+                autotune.tune_batch_two_step(batch)
         tx2, ty2, nb2 = batch.two_step_shape()
         two = tx2 > 0
         log(f"bench: batch of {len(lats)} lattices, {sites} sites, tile {tx}x{ty}x{tr}, "

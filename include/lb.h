@@ -231,6 +231,13 @@ int lb_batch_use_graphs(lb_batch* b, int enable);
  * runs one step per launch.  Any output may be NULL. */
 int lb_batch_two_step_shape(lb_batch* b, int32_t* tile_x, int32_t* tile_y, int32_t* blocks);
 
+/* Rows per workgroup of the batch's two-step launches: tile_y in [8, 64], or
+ * 0 for the library's choice (the tallest of 48, 32, 24, 16 rows giving at
+ * least 1400 workgroups).  Only the launch shape changes: fields stay
+ * bit-identical.  Synchronises the stream and drops captured graphs.
+ * LB_ERR_STATE if the batch runs one step per launch. */
+int lb_batch_two_step_tile(lb_batch* b, int32_t tile_y);
+
 /* Context of lattice i, owned by the batch: lb_moments, lb_pseudo_energy,
  * lb_trace, lb_time and lb_get_state accept it; lb_step, lb_set_state and
  * lb_destroy reject it with LB_ERR_STATE. */

@@ -17,6 +17,13 @@ import numpy as np
 DEFAULT_CANDIDATES = [(256, 32, 1), (256, 16, 1), (128, 32, 1), (256, 32, 2), (128, 16, 1),
                       (64, 32, 1), (256, 64, 2), (256, 8, 1), (128, 8, 1), (256, 4, 1),
                       (64, 4, 1), (256, 2, 1)]
+# Two-step launches, (tile_x, tile_y): a workgroup of tile_x lanes makes
+# tile_x - 6 columns.  A workgroup walks its rows one after another, so the
+# heights around "every tile resident in one round" matter most.
+TWO_STEP_CANDIDATES = [(128, h) for h in (8, 12, 16, 20, 23, 24, 28, 32, 40, 48)] + \
+                      [(256, h) for h in (24, 32, 40, 44, 46, 48)]
+# Two-step tile heights of a batch (its tiles are 128 lanes wide).
+BATCH_TWO_STEP_HEIGHTS = (16, 24, 32, 40, 48, 56, 64)
 
 
 def cache_path():
@@ -42,17 +49,18 @@ def _save(d):
     os.replace(tmp, path)
 
 
-def time_shape(nx, ny, storage, tile_x, tile_y, tile_rows, steps=100, warmup=20):
-    """Microseconds per step of the step kernel for one launch shape."""
+def time_shape(nx, ny, storage, tile_x, tile_y, tile_rows, steps=100, warmup=20,
+               steps_per_launch=1):
+    """Microseconds per step for one launch shape: of the one-step kernel
+    (steps_per_launch = 1), or of the two-step kernel (2; tile_rows unused)."""
     import torch
 
     from . import inputs
     from .sim import LBSim
 
     G1, G2 = inputs.couplings(0.1)
-    # One step per launch: the shape tuned here is that of the one-step kernel.
     sim = LBSim(inputs.rho_noise(nx, ny, 1), G1=G1, G2=G2, storage=storage, tile_x=tile_x,
-                tile_y=tile_y, tile_rows=tile_rows, steps_per_launch=1)
+                tile_y=tile_y, tile_rows=tile_rows, steps_per_launch=steps_per_launch)
     sim.step(warmup)
     a = torch.cuda.Event(enable_timing=True)
     b = torch.cuda.Event(enable_timing=True)
@@ -64,8 +72,12 @@ def time_shape(nx, ny, storage, tile_x, tile_y, tile_rows, steps=100, warmup=20)
     return a.elapsed_time(b) * 1e3 / steps
 
 
-def tune(nx, ny, storage="f32", candidates=None, refresh=False, steps=100):
-    """Fastest (tile_x, tile_y, tile_rows) for this size and storage."""
+def tune(nx, ny, storage="f32", candidates=None, refresh=False, steps=100, steps_per_launch=1):
+    """Fastest (tile_x, tile_y, tile_rows) for this size and storage: of the
+    one-step kernel, or with steps_per_launch = 2 of the two-step kernel
+    (candidates (tile_x, tile_y); tile_rows is returned as 1)."""
+    if steps_per_launch == 2:
+        return _tune_two_step(nx, ny, storage, candidates, refresh, steps)
     key = f"{storage}:{nx}x{ny}"
     cache = _load()
     if not refresh and key in cache:
@@ -84,6 +96,60 @@ def tune(nx, ny, storage="f32", candidates=None, refresh=False, steps=100):
     cache[key] = {"tile_x": best[1], "tile_y": best[2], "tile_rows": best[3], "us_per_step": best[0]}
     _save(cache)
     return best[1], best[2], best[3]
+
+
+def _tune_two_step(nx, ny, storage, candidates, refresh, steps):
+    key = f"{storage}:{nx}x{ny}:two-step"
+    cache = _load()
+    if not refresh and key in cache:
+        c = cache[key]
+        return c["tile_x"], c["tile_y"], 1
+    best = None
+    for tx, ty in (candidates or TWO_STEP_CANDIDATES):
+        if tx - 6 > nx or ty > ny:
+            continue
+        us = time_shape(nx, ny, storage, tx, ty, 1, steps=steps, steps_per_launch=2)
+        if best is None or us < best[0]:
+            best = (us, tx, ty)
+    cache[key] = {"tile_x": best[1], "tile_y": best[2], "us_per_step": best[0]}
+    _save(cache)
+    return best[1], best[2], 1
+
+
+def tune_batch_two_step(batch, heights=BATCH_TWO_STEP_HEIGHTS, refresh=False, steps=20):
+    """Set the fastest two-step tile height on a batch that runs plain steps
+    two per launch (timed on the batch itself, every lattice in each launch)
+    and return it; 0 when the batch runs one step per launch.  The batch
+    advances while it is timed."""
+    import hashlib
+
+    import torch
+
+    if batch.two_step_shape()[0] == 0:
+        return 0
+    sig = hashlib.sha1(repr(sorted(batch.shapes)).encode()).hexdigest()[:12]
+    key = f"batch-two-step:{batch.storage}:{len(batch.shapes)}:{sig}"
+    cache = _load()
+    if not refresh and key in cache:
+        batch.set_two_step_tile(cache[key]["tile_y"])
+        return cache[key]["tile_y"]
+    best = None
+    for ty in heights:
+        batch.set_two_step_tile(ty)
+        batch.step(4)  # capture (graphs) and warm up
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        batch.step(steps)
+        b.record()
+        torch.cuda.synchronize()
+        us = a.elapsed_time(b) * 1e3 / steps
+        if best is None or us < best[0]:
+            best = (us, ty)
+    batch.set_two_step_tile(best[1])
+    cache[key] = {"tile_y": best[1], "us_per_step": best[0]}
+    _save(cache)
+    return best[1]
 
 
 def tune_batch(lattices, storage="f32", tile_x=None, tile_ys=(8, 16, 32, 64), tile_rows=(1, 2),

@@ -72,6 +72,7 @@ SIGNATURES = {
     "lb_batch_step": (ctypes.c_int, [_vp, ctypes.c_int64]),
     "lb_batch_use_graphs": (ctypes.c_int, [_vp, ctypes.c_int]),
     "lb_batch_two_step_shape": (ctypes.c_int, [_vp, _vp, _vp, _vp]),
+    "lb_batch_two_step_tile": (ctypes.c_int, [_vp, ctypes.c_int32]),
     "lb_batch_member": (ctypes.c_int, [_vp, ctypes.c_int32, ctypes.POINTER(_vp)]),
     "lb_batch_destroy": (ctypes.c_int, [_vp]),
     "lb_adj_workspace_bytes": (ctypes.c_size_t, [_P, ctypes.c_int64, ctypes.c_int32]),
@@ -237,6 +238,10 @@ def lb_batch_step(b, n):
 
 def lb_batch_use_graphs(b, enable):
     return _check(lib().lb_batch_use_graphs(b, int(bool(enable))))
+
+
+def lb_batch_two_step_tile(b, tile_y):
+    return _check(lib().lb_batch_two_step_tile(b, int(tile_y)))
 
 
 def lb_batch_two_step_shape(b):

@@ -160,10 +160,18 @@ Geom make_geom(const lb_params& p)
 // tile_x - 6 columns (the first step also covers 3 columns each side).
 // Explicit tile_x / tile_y apply to both kernels; the library's choice
 // follows.
-// Workgroups of the two-step kernel resident at once: 3 waves per SIMD (its
-// registers and LDS), i.e. 6 of 128 lanes or 3 of 256 lanes per CU, on the
-// 256 CUs of the MI355X.
-int64_t step2_slots(int tile_x) { return 256 * (tile_x == 256 ? 3 : 6); }
+// Workgroups of the two-step kernel resident at once: the runtime's
+// occupancy query on the current device (registers and LDS of the kernel as
+// built) times its compute units.  Without a device to ask, the value for
+// the MI355X as the kernel is built today: 3 waves per SIMD, i.e. 6
+// workgroups of 128 lanes or 3 of 256 lanes per CU, on 256 CUs (a GPU test
+// holds this to the occupancy query).
+int64_t step2_slots_fallback(int tile_x) { return 256 * (tile_x == 256 ? 3 : 6); }
+int64_t step2_slots(int storage, int tile_x)
+{
+    const int r = lbk::step2_resident(storage == LB_F16DEV ? LB_F16DEV : LB_F32, tile_x);
+    return r > 0 ? r : step2_slots_fallback(tile_x);
+}
 
 // Two-step launch shape.  A workgroup walks its rows one after the other,
 // so while every tile is resident at once (one round), shorter tiles finish
@@ -186,7 +194,7 @@ Geom make_geom2(const lb_params& p, const Geom& g)
         int one_x = 0, one_y = 0;
         for (int c : {128, 256}) {
             if (tx && tx != c) continue;
-            const int64_t per_strip = step2_slots(c) / strips(c);
+            const int64_t per_strip = step2_slots(p.storage, c) / strips(c);
             if (per_strip < 1) continue;
             const int64_t h = (p.ny + per_strip - 1) / per_strip;
             if (h <= 48) {
@@ -202,7 +210,7 @@ Geom make_geom2(const lb_params& p, const Geom& g)
             if (!tx) tx = 256;
             if (!ty) {
                 ty = 48;
-                const int64_t slots = step2_slots(tx);
+                const int64_t slots = step2_slots(p.storage, tx);
                 const int64_t rounds = (strips(tx) * rows(48) + slots - 1) / slots;
                 const int64_t per_strip = rounds * slots / strips(tx);
                 const int fit = per_strip > 0 ? (int)((p.ny + per_strip - 1) / per_strip) : 48;
@@ -292,6 +300,9 @@ struct lb_batch {
     int64_t t, log_every, trace_cap, trace_rows, last_logged;
     bool use_graphs;
     std::map<std::pair<int64_t, int>, hipGraphExec_t> graphs;
+    std::vector<lb_params> params;           // per lattice, as given to lb_batch_init
+    std::vector<lbk::BatchLattice> host_desc;  // host copy of desc
+    int tiles2_cap;                          // capacity of tile_lattice2
 };
 
 namespace {
@@ -750,10 +761,15 @@ struct BatchLayout {
     size_t desc, tile_lattice, tile_lattice2, partials;
     std::vector<size_t> member, member_bytes;
     size_t total;
-    int tiles, tiles2, tile_y2;
+    int tiles, tiles2, tiles2_cap, tile_y2;
     bool two;
     std::vector<Geom> geom2;
 };
+
+// Smallest two-step tile height of a batch: the two-step tile table is
+// sized for it, so the height can change after initialisation.
+constexpr int kBatchMinTile2 = 8;
+constexpr int kBatchMaxTile2 = 64;
 
 // Two-step geometry of a batch member: 128-lane tiles and a tile height
 // shared by the batch.
@@ -810,19 +826,23 @@ int batch_layout(const lb_params* ps, int32_t count, BatchLayout* L)
     if (L->two && tile_y2 == 0) tile_y2 = 8;
     L->tile_y2 = L->two ? tile_y2 : 0;
     L->tiles2 = 0;
+    L->tiles2_cap = 0;
     L->geom2.assign(count, Geom{});
     if (L->two)
         for (int32_t i = 0; i < count; ++i) {
             L->geom2[i] = batch_geom2(ps[i], tile_y2);
             L->tiles2 += L->geom2[i].blocks;
+            L->tiles2_cap += batch_geom2(ps[i], kBatchMinTile2).blocks;
         }
+    if ((int64_t)L->tiles2_cap >= (int64_t(1) << 30))
+        return fail(LB_ERR_INVALID, "too many two-step tiles in the batch");
     size_t off = 0;
     L->desc = off;
     off += align_up(sizeof(lbk::BatchLattice) * count);
     L->tile_lattice = off;
     off += align_up(sizeof(int32_t) * L->tiles);
     L->tile_lattice2 = off;
-    off += align_up(sizeof(int32_t) * L->tiles2);
+    off += align_up(sizeof(int32_t) * L->tiles2_cap);
     L->partials = off;
     off += align_up(sizeof(double) * 4 * L->tiles);
     L->member.resize(count);
@@ -1061,6 +1081,9 @@ int lb_batch_init(lb_batch** out, const lb_params* ps, int32_t count, void* work
     b->trace_rows = 0;
     b->last_logged = -1;
     b->use_graphs = b->stream != nullptr && b->storage != LB_F16DEV;
+    b->params.assign(ps, ps + count);
+    b->host_desc = desc;
+    b->tiles2_cap = L.tiles2_cap;
     hipError_t e = hipMemcpyAsync(b->desc, desc.data(), sizeof(lbk::BatchLattice) * count,
                                   hipMemcpyHostToDevice, b->stream);
     if (!e) e = hipMemcpyAsync(b->tile_lattice, tl.data(), sizeof(int32_t) * L.tiles,
@@ -1131,6 +1154,45 @@ int lb_batch_two_step_shape(lb_batch* b, int32_t* tile_x, int32_t* tile_y, int32
     if (tile_x) *tile_x = b->two ? b->tile_x2 : 0;
     if (tile_y) *tile_y = b->two ? b->tile_y2 : 0;
     if (blocks) *blocks = b->two ? b->tiles2 : 0;
+    return LB_OK;
+}
+
+int lb_batch_two_step_tile(lb_batch* b, int32_t tile_y)
+{
+    int rc = check_batch(b);
+    if (rc) return rc;
+    if (!b->two) return fail(LB_ERR_STATE, "this batch runs one step per launch");
+    if (tile_y != 0 && (tile_y < kBatchMinTile2 || tile_y > kBatchMaxTile2))
+        return fail(LB_ERR_INVALID, "tile_y must be 0 or in [%d, %d] (got %d)", kBatchMinTile2,
+                    kBatchMaxTile2, tile_y);
+    const int count = (int)b->members.size();
+    BatchLayout L;
+    if ((rc = batch_layout(b->params.data(), count, &L))) return rc;
+    const int ty = tile_y ? tile_y : L.tile_y2;
+    std::vector<lbk::BatchLattice> desc = b->host_desc;
+    std::vector<int32_t> tl2;
+    tl2.reserve(b->tiles2_cap);
+    for (int i = 0; i < count; ++i) {
+        desc[i].geom2 = batch_geom2(b->params[i], ty);
+        desc[i].tile_begin2 = (int32_t)tl2.size();
+        tl2.insert(tl2.end(), desc[i].geom2.blocks, i);
+    }
+    if ((int)tl2.size() > b->tiles2_cap) return fail(LB_ERR_INVALID, "two-step tile table too small");
+    DeviceGuard dg(b->device);
+    if (dg.err) return hip_fail(dg.err, "select device");
+    // Work already issued reads the tables: let it finish before rewriting them.
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (!e) e = hipMemcpyAsync(b->desc, desc.data(), sizeof(lbk::BatchLattice) * count,
+                               hipMemcpyHostToDevice, b->stream);
+    if (!e) e = hipMemcpyAsync(b->tile_lattice2, tl2.data(), sizeof(int32_t) * tl2.size(),
+                               hipMemcpyHostToDevice, b->stream);
+    if (!e) e = hipStreamSynchronize(b->stream);
+    if (e) return hip_fail(e, "copy batch tables");
+    for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
+    b->graphs.clear();  // captured launches carry the old grid
+    b->host_desc = desc;
+    b->tile_y2 = ty;
+    b->tiles2 = (int)tl2.size();
     return LB_OK;
 }
 

@@ -87,6 +87,11 @@ hipError_t launch_step2(int storage, const void* src, void* dst, const Geom& g, 
 hipError_t launch_step2_batch(int storage, int tile_x, const BatchLattice* desc,
                               const int32_t* tile_lattice, int tiles, int parity, uint32_t step,
                               hipStream_t s);
+// Workgroups of tile_x lanes of the two-step kernel (ST_F32 or ST_F16DEV)
+// resident on the current device at once: the runtime's occupancy for the
+// kernel's registers and LDS, per compute unit, times the compute units.
+// -1 when no device can be asked.
+int step2_resident(int storage, int tile_x);
 hipError_t launch_final(const double* partials, int blocks, double t,
                         double half_A1, double* out_row, hipStream_t s);
 hipError_t launch_step_batch(int storage, int mode, int tile_x, int rows_per_iter, int min_tile_y,

@@ -24,6 +24,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <type_traits>
 
 namespace lbk {
@@ -1209,6 +1212,42 @@ hipError_t launch_step2(int storage, const void* src, void* dst, const Geom& g, 
     case ST_F16DEV: return step2_p<PF16>(src, dst, g, c, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+namespace {
+template <class P>
+const void* step2_kernel(int tile_x)
+{
+    switch (tile_x) {
+    case 64: return reinterpret_cast<const void*>(k_step2<P, 64>);
+    case 128: return reinterpret_cast<const void*>(k_step2<P, 128>);
+    case 256: return reinterpret_cast<const void*>(k_step2<P, 256>);
+    default: return nullptr;
+    }
+}
+}  // namespace
+
+int step2_resident(int storage, int tile_x)
+{
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, int> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return -1;
+    const auto key = std::make_tuple(dev, storage, tile_x);
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(key);
+    if (it != cache.end()) return it->second;
+    const void* fn = storage == ST_F32 ? step2_kernel<PF32>(tile_x)
+                   : storage == ST_F16DEV ? step2_kernel<PF16>(tile_x) : nullptr;
+    int cus = 0, per_cu = 0;
+    if (!fn || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, tile_x, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    const int r = cus > 0 && per_cu > 0 ? cus * per_cu : -1;
+    cache.emplace(key, r);
+    return r;
 }
 
 hipError_t launch_step_batch(int storage, int mode, int tile_x, int rows_per_iter, int min_tile_y,

@@ -198,6 +198,7 @@ class LBBatch:
         self.members = [_Member(self, i, nx, ny, storage, trace_cap)
                         for i, (ny, nx) in enumerate(self.shapes)]
         self.sites = sum(nx * ny for ny, nx in self.shapes)
+        self.storage = storage
 
     def step(self, n=1):
         B.lb_batch_step(self.b, n)
@@ -205,6 +206,10 @@ class LBBatch:
     def two_step_shape(self):
         """(tile_x, tile_y, workgroups) of the two-step launches, zeros if unused."""
         return B.lb_batch_two_step_shape(self.b)
+
+    def set_two_step_tile(self, tile_y):
+        """Rows per workgroup of the two-step launches (0: the library's choice)."""
+        B.lb_batch_two_step_tile(self.b, tile_y)
 
     def __getitem__(self, i):
         return self.members[i]

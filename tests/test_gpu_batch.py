@@ -72,6 +72,37 @@ def test_batch_matches_single_lattice_runs(use_graphs, storage, tile_rows, spl):
         batch.close()
 
 
+def test_two_step_tile_height_changes_nothing_but_the_shape():
+    # The two-step tile height is set between steps (and the captured graphs
+    # dropped with it): the fields stay bit-identical to single-lattice runs.
+    lats = lattices(30)[:4]
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        batch = LBBatch(lats, storage="f32", tile_x=64, log_every=10, max_steps=90,
+                        steps_per_launch=2)
+        for ty, n in ((16, 31), (40, 30), (8, 29)):
+            batch.set_two_step_tile(ty)
+            assert batch.two_step_shape()[:2] == (128, ty)
+            batch.step(n)
+        for k, L in enumerate(lats):
+            single = LBSim(L["rho_init"], G1=L["G1"], G2=L["G2"], tau=L["tau"], storage="f32",
+                           tile_x=64, tile_y=L["tile_y"], log_every=10, max_steps=90)
+            single.step(90)
+            assert np.array_equal(batch[k].get_state().view(np.uint32),
+                                  single.get_state().view(np.uint32)), k
+            assert np.array_equal(batch[k].trace(), single.trace()), k
+            single.close()
+        with pytest.raises(B.LBError) as e:
+            batch.set_two_step_tile(7)
+        assert e.value.code == B.LB_ERR_INVALID
+        batch.close()
+        one = LBBatch(lats, storage="f32", tile_x=64, steps_per_launch=1)
+        with pytest.raises(B.LBError) as e:
+            one.set_two_step_tile(16)
+        assert e.value.code == B.LB_ERR_STATE
+        one.close()
+
+
 def test_batch_against_oracle():
     lats = lattices(20)[:4]
     batch = LBBatch(lats, storage="f64", tile_x=64)

@@ -88,3 +88,16 @@ def test_half_storage_decodes_identically_everywhere():
         kw = dict(tile_x=tx, tile_y=ty) | ({"tile_rows": tr} if tr else {})
         s, _ = run(rho0, 61, spl, storage="f16dev", **kw)
         assert np.array_equal(s.view(np.uint16), ref.view(np.uint16))
+
+
+def test_two_step_residency_matches_the_occupancy_query():
+    # The two-step shape rule sizes tiles by the workgroups resident at once.
+    # On the device it asks the runtime's occupancy query; without one it
+    # uses the value for the kernel as built (6 workgroups of 128 lanes per
+    # CU on 256 CUs).  Both must agree, or the CPU-side value is stale.
+    from paper_1008_2865_amd import binding as B
+
+    p = B.make_params(2048, 2048, storage=B.LB_F32, G1=-5.4, G2=0.54)
+    assert B.lb_two_step_shape(p) == (128, 23, 1530)
+    p = B.make_params(3000, 3000, storage=B.LB_F32, G1=-5.4, G2=0.54)
+    assert B.lb_two_step_shape(p)[:2] == (256, 47)

@@ -87,19 +87,6 @@ __device__ __forceinline__ uint32_t site_hash(uint32_t x, uint32_t y, uint32_t t
     return h;
 }
 
-// float -> half with stochastic rounding: the 13 mantissa bits half drops
-// are replaced by a carry from r, so the result rounds up with probability
-// equal to the dropped fraction (unbiased).  Outside the half normal range
-// it falls back to round-to-nearest.
-__device__ __forceinline__ _Float16 half_stochastic(float v, uint32_t r)
-{
-    const uint32_t b = __float_as_uint(v);
-    uint32_t mag = b & 0x7fffffffu;
-    if (mag < 0x38800000u || mag >= 0x477fe000u) return (_Float16)v;
-    mag = (mag + (r & 0x1fffu)) & ~0x1fffu;
-    return (_Float16)__uint_as_float((b & 0x80000000u) | mag);
-}
-
 template <typename C>
 struct CoefT {
     C K1, K2, K4, K5, K8, KE0, tau, omega, sqrt_rho0, inv_rho0, rho_ref;
@@ -151,48 +138,81 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
                      : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-// Deviation offsets w_i rho_ref of the half storage (zero otherwise).
+// Deviation offsets w_i rho_ref of the half storage (zero otherwise), and
+// the decoding of a stored value.
 template <class P>
 struct Offs {
-    typename P::C o0, o1, o2;  // rest, axis, diagonal
-    __device__ Offs(typename P::C rho_ref)
+    using S = typename P::S;
+    using C = typename P::C;
+    C o0, o1, o2;  // rest, axis, diagonal
+    C osum;        // o0 + 4 o1 + 4 o2, the offsets of all nine populations
+    _Float16 one;  // 1, opaque to the compiler (see ld)
+    __device__ Offs(C rho_ref)
     {
 #pragma clang fp contract(off)
-        using C = typename P::C;
         // Each offset is the rounded product; no later add may absorb it.
         if (P::kDev) {
             o0 = rho_ref * ((C)4 / (C)9);
             o1 = rho_ref * ((C)1 / (C)9);
             o2 = rho_ref * ((C)1 / (C)36);
+            osum = (o0 + (C)4 * o1) + (C)4 * o2;
         } else {
-            o0 = o1 = o2 = (C)0;
+            o0 = o1 = o2 = osum = (C)0;
         }
+        one = (_Float16)1;
+        asm("" : "+v"(one));
     }
-    __device__ typename P::C of(int i) const { return i == 0 ? o0 : (i < 5 ? o1 : o2); }
+    __device__ C of(int i) const { return i == 0 ? o0 : (i < 5 ? o1 : o2); }
+    // A stored value as the arithmetic type.  Half storage: off + h rounded
+    // once, written as the fma h * 1 + off (the product is exact) with a
+    // half-precision 1 the compiler cannot fold, so that it becomes a single
+    // mixed-precision fma instead of a conversion and an add: the same value.
+    __device__ C dec(S v, C off) const
+    {
+        if constexpr (P::kDev)
+            return __builtin_fmaf((float)v, (float)one, off);
+        else
+            return v;
+    }
+    __device__ C ld(const S* p, C off) const { return dec(*p, off); }
 };
+
+// float -> half with stochastic rounding in hardware: the conversion adds
+// random bits (the high bits of r) below the kept mantissa before
+// truncating, so it rounds up with probability equal to the dropped
+// fraction (unbiased), for normal and subnormal halves alike.
+__device__ __forceinline__ _Float16 half_stochastic_hw(float v, uint32_t r)
+{
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    const half2_t z = {};
+    return __builtin_amdgcn_cvt_sr_f16_f32(z, v, r, false)[0];
+}
 
 // Store the nine post-collision populations of one site.  For the half
 // storage the moving populations are rounded to nearest, and the rest
 // population absorbs their rounding errors (so the stored populations of a
 // site sum to its density up to a single rounding) and is itself rounded
 // stochastically: at a uniform state every site would otherwise make the
-// same rounding error at every step and the total mass would drift.
+// same rounding error at every step and the total mass would drift.  For
+// the half storage q[0] is the density (site_collide<..., true>).
 template <class P>
 __device__ __forceinline__ void store_site(typename P::S* const* pd, int at,
                                            const typename P::C q[9],
                                            const Offs<P>& o, uint32_t rnd)
 {
     if constexpr (P::kDev) {
+        // q[0] holds rho.  The rest population is stored as what the rounded
+        // moving populations leave of rho, so the nine decoded values sum to
+        // rho up to the rounding of the rest itself.
 #pragma clang fp contract(off)
-        float resid = q[0] - o.o0;
+        float resid = q[0] - o.osum;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const float d = q[i] - o.of(i);
-            const _Float16 h = (_Float16)d;
-            resid += d - (float)h;
+            const _Float16 h = (_Float16)(q[i] - o.of(i));
+            resid = __builtin_fmaf(-(float)h, (float)o.one, resid);  // exact product: resid - h
             pd[i][at] = h;
         }
-        pd[0][at] = half_stochastic(resid, rnd);
+        pd[0][at] = half_stochastic_hw(resid, rnd);
     } else {
 #pragma unroll
         for (int i = 0; i < 9; ++i) P::st(pd[i] + at, q[i], o.of(i));
@@ -211,15 +231,15 @@ __device__ __forceinline__ void pull(const typename P::S* const* pl,
     const int yp = y == g.ny - 1 ? 0 : y + 1;
     // Offsets inside one plane fit in 32 bits (the host checks it).
     const int r0 = y * g.pitch, rm = ym * g.pitch, rp = yp * g.pitch;
-    f[0] = P::ld(pl[0] + r0 + x, o.o0);
-    f[1] = P::ld(pl[1] + r0 + xm, o.o1);  // c = ( 1, 0)
-    f[2] = P::ld(pl[2] + rm + x, o.o1);   // c = ( 0, 1)
-    f[3] = P::ld(pl[3] + r0 + xp, o.o1);  // c = (-1, 0)
-    f[4] = P::ld(pl[4] + rp + x, o.o1);   // c = ( 0,-1)
-    f[5] = P::ld(pl[5] + rm + xm, o.o2);  // c = ( 1, 1)
-    f[6] = P::ld(pl[6] + rm + xp, o.o2);  // c = (-1, 1)
-    f[7] = P::ld(pl[7] + rp + xp, o.o2);  // c = (-1,-1)
-    f[8] = P::ld(pl[8] + rp + xm, o.o2);  // c = ( 1,-1)
+    f[0] = o.ld(pl[0] + r0 + x, o.o0);
+    f[1] = o.ld(pl[1] + r0 + xm, o.o1);  // c = ( 1, 0)
+    f[2] = o.ld(pl[2] + rm + x, o.o1);   // c = ( 0, 1)
+    f[3] = o.ld(pl[3] + r0 + xp, o.o1);  // c = (-1, 0)
+    f[4] = o.ld(pl[4] + rp + x, o.o1);   // c = ( 0,-1)
+    f[5] = o.ld(pl[5] + rm + xm, o.o2);  // c = ( 1, 1)
+    f[6] = o.ld(pl[6] + rm + xp, o.o2);  // c = (-1, 1)
+    f[7] = o.ld(pl[7] + rp + xp, o.o2);  // c = (-1,-1)
+    f[8] = o.ld(pl[8] + rp + xm, o.o2);  // c = ( 1,-1)
 }
 
 template <typename C>
@@ -280,32 +300,33 @@ struct Stencil {
 // the pre-collision populations, st the psi stencil around the site, Q the
 // post-collision populations; with kTape also the tape entry.  Every kernel
 // that updates a site calls this, so all of them round identically.
-template <bool kTape, typename C>
+template <bool kTape, bool kRestIsRho, typename C>
 __device__ __forceinline__ void site_collide(const C (&R)[9], const Stencil<C>& st, const CoefT<C>& k,
                                              C (&Q)[9], C* tp)
 {
 #pragma clang fp contract(off)
     // Multiply-adds are written out as fma and nothing else is contracted,
     // so every kernel variant (launch shape, batched or not, one or two
-    // steps per launch) rounds each site's update identically.
-    const C p = st.p, e1 = st.e1, w1 = st.w1, n1 = st.n1, s1v = st.s1v, ne = st.ne, nw = st.nw,
-            sw = st.sw, se = st.se, e2 = st.e2, w2 = st.w2, n2 = st.n2, s2v = st.s2v, e2n = st.e2n,
-            e2s = st.e2s, w2n = st.w2n, w2s = st.w2s, n2e = st.n2e, n2w = st.n2w, s2e = st.s2e,
-            s2w = st.s2w, ne2 = st.ne2, nw2 = st.nw2, sw2 = st.sw2, se2 = st.se2;
-    // eq. (FORCE): F = -psi(x) sum_k K_k psi(x + c_k) c_k, links
-    // paired with their opposites.
+    // steps per launch, one or two sites per lane) rounds each site's update
+    // identically.
+    const C p = st.p;
+    // eq. (FORCE): F = -psi(x) sum_k K_k psi(x + c_k) c_k, links paired with
+    // their opposites.  The differences of opposite links off the axes
+    // (|c|^2 = 2, 5, 8) enter both components, so they are formed once.
+    const C d2a = st.ne - st.sw, d2b = st.se - st.nw;      // (1, 1), (1,-1)
+    const C d8a = st.ne2 - st.sw2, d8b = st.se2 - st.nw2;  // (2, 2), (2,-2)
+    const C d5a = st.e2n - st.w2s, d5b = st.e2s - st.w2n;  // (2, 1), (2,-1)
+    const C d5c = st.n2e - st.s2w, d5d = st.n2w - st.s2e;  // (1, 2), (-1, 2)
     const C sumx =
-        fma_c(k.K1, e1 - w1,
-              fma_c(k.K2, (ne + se) - (nw + sw),
-                    fma_c(k.K4x2, e2 - w2,
-                          fma_c(k.K5, fma_c((C)2, (e2n + e2s) - (w2n + w2s), (n2e + s2e) - (n2w + s2w)),
-                                k.K8x2 * ((ne2 + se2) - (nw2 + sw2))))));
+        fma_c(k.K1, st.e1 - st.w1,
+              fma_c(k.K2, d2a + d2b,
+                    fma_c(k.K4x2, st.e2 - st.w2,
+                          fma_c(k.K5, fma_c((C)2, d5a + d5b, d5c - d5d), k.K8x2 * (d8a + d8b)))));
     const C sumy =
-        fma_c(k.K1, n1 - s1v,
-              fma_c(k.K2, (ne + nw) - (se + sw),
-                    fma_c(k.K4x2, n2 - s2v,
-                          fma_c(k.K5, fma_c((C)2, (n2e + n2w) - (s2e + s2w), (e2n + w2n) - (e2s + w2s)),
-                                k.K8x2 * ((ne2 + nw2) - (se2 + sw2))))));
+        fma_c(k.K1, st.n1 - st.s1v,
+              fma_c(k.K2, d2a - d2b,
+                    fma_c(k.K4x2, st.n2 - st.s2v,
+                          fma_c(k.K5, fma_c((C)2, d5c + d5d, d5a - d5b), k.K8x2 * (d8a - d8b)))));
     const C Fx = -p * sumx;
     const C Fy = -p * sumy;
 
@@ -326,20 +347,29 @@ __device__ __forceinline__ void site_collide(const C (&R)[9], const Stencil<C>& 
     const C base = fma_c((C)-1.5, fma_c(ux, ux, uy * uy), (C)1);
     const C r1 = rho * ((C)1 / (C)9);
     const C r2 = rho * ((C)1 / (C)36);
-    const C om = k.omega;
     auto feq = [&](C r, C cu) { return r * fma_c(cu, fma_c((C)4.5, cu, (C)3), base); };
-    auto relax = [&](C f, C fe) { return fma_c(om, fe - f, f); };
-    Q[1] = relax(R[1], feq(r1, ux));
-    Q[2] = relax(R[2], feq(r1, uy));
-    Q[3] = relax(R[3], feq(r1, -ux));
-    Q[4] = relax(R[4], feq(r1, -uy));
-    Q[5] = relax(R[5], feq(r2, ux + uy));
-    Q[6] = relax(R[6], feq(r2, uy - ux));
-    Q[7] = relax(R[7], feq(r2, -ux - uy));
-    Q[8] = relax(R[8], feq(r2, ux - uy));
-    // The collision conserves mass exactly; take the rest
-    // population from that so rounding cannot drift the mass.
-    Q[0] = rho - (((Q[1] + Q[3]) + (Q[2] + Q[4])) + ((Q[5] + Q[7]) + (Q[6] + Q[8])));
+    Q[1] = feq(r1, ux);
+    Q[2] = feq(r1, uy);
+    Q[3] = feq(r1, -ux);
+    Q[4] = feq(r1, -uy);
+    Q[5] = feq(r2, ux + uy);
+    Q[6] = feq(r2, uy - ux);
+    Q[7] = feq(r2, -ux - uy);
+    Q[8] = feq(r2, ux - uy);
+    // f* = f + (f_eq - f) / tau; at tau = 1 (every run of the paper) that is
+    // f_eq itself.  The branch is uniform.
+    if (k.omega != (C)1) {
+        const C om = k.omega;
+#pragma unroll
+        for (int i = 1; i < 9; ++i) Q[i] = fma_c(om, Q[i] - R[i], R[i]);
+    }
+    // The collision conserves mass exactly; the rest population is taken
+    // from that, so rounding cannot drift the mass.  The half storage forms
+    // it when it rounds the moving populations: there Q[0] carries rho.
+    if (kRestIsRho)
+        Q[0] = rho;
+    else
+        Q[0] = rho - (((Q[1] + Q[3]) + (Q[2] + Q[4])) + ((Q[5] + Q[7]) + (Q[6] + Q[8])));
 }
 
 template <int J>
@@ -444,7 +474,7 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
         const int ym = y == 0 ? ny - 1 : y - 1;
         const int yp = y == ny - 1 ? 0 : y + 1;
         const int r = (hcy > 0 ? ym : (hcy < 0 ? yp : y)) * g.pitch;
-        return P::ld(hp + r, hoff);
+        return o.ld(hp + r, hoff);
     };
     auto halo_psi = [&](C hv, int slot) {
         C h[9];
@@ -555,8 +585,8 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
             }
 
             if (kCollide) {
-                site_collide<kTape>(R, st, k, q[m], tp[m]);
-                if (m == 0) anchor = q[m][0];
+                site_collide<kTape, P::kDev>(R, st, k, q[m], tp[m]);
+                if (m == 0) anchor = q[m][1];
             } else if (m == 0) {
                 anchor = p;
             }
@@ -731,7 +761,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
         const int ym = y == 0 ? ny - 1 : y - 1;
         const int yp = y == ny - 1 ? 0 : y + 1;
         const int r = (hcy > 0 ? ym : (hcy < 0 ? yp : y)) * g.pitch;
-        return P::ld(hp + r, hoff);
+        return o.ld(hp + r, hoff);
     };
     auto halo_psi = [&](C hv, int slot) {
         C h[9];
@@ -790,7 +820,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
                 // form values no output uses).
                 const int rr = p - 2 - q_cy(i) * dir;
                 const int li = min(max(tid - q_cx(i), 0), NT - 1);
-                Fr[i] = P::ld(&fs[(rr + 4) & 3][i][li], o.of(i));
+                Fr[i] = o.ld(&fs[(rr + 4) & 3][i][li], o.of(i));
             }
             ring2[(p - 2 + 12) % RS2][tid + 2] = psi_of(density(Fr), k2);
         }
@@ -805,13 +835,13 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             const Stencil<C> st(ring[slot(-2)], ring[slot(-1)], ring[slot(0)], ring[slot(1)],
                                 ring[slot(2)], tid + 2);
             C q[9];
-            site_collide<false>(Bf[J % 4], st, k, q, (C*)nullptr);
+            site_collide<false, P::kDev>(Bf[J % 4], st, k, q, (C*)nullptr);
             S* lp[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) lp[i] = &fs[(p + 4) & 3][i][0];
             const uint32_t rnd = P::kDev ? site_hash(xc, wrow(p), k.step) : 0u;
             store_site<P>(lp, tid, q, o, rnd);
-            anchor = q[0];
+            anchor = q[1];
         }
 
         // Stage psi at t of the lead row p + 3.
@@ -843,7 +873,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             const C* r_p2 = ring2[dir > 0 ? s2(2) : s2(-2)];
             const Stencil<C> st2(r_m2, r_m1, r_c, r_p1, r_p2, tid + 2);
             C q2[9];
-            site_collide<false>(F2[J % 4], st2, k2, q2, (C*)nullptr);
+            site_collide<false, P::kDev>(F2[J % 4], st2, k2, q2, (C*)nullptr);
             if (own2) {
                 const int yq = wrow(qr);
                 const int xq = x0 + tid - 3;

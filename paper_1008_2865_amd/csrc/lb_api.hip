@@ -1253,6 +1253,12 @@ struct lb_adj {
     int32_t tape_seg;     // segment whose tape the tape region holds, or -1
     bool have_forward;
     double E, A, E_target, beta, eps;
+    // Full backward segments replay a captured graph (keyed by the parity of
+    // the adjoint buffers at its start), valid for the couplings it was
+    // captured with.
+    std::map<int, hipGraphExec_t> seg_graphs;
+    double graph_G1, graph_G2;
+    bool use_graphs;
 };
 
 namespace {
@@ -1275,6 +1281,76 @@ int adj_tape_steps(lb_adj* a, int64_t n)
         ++c->t;
     }
     return LB_OK;
+}
+
+void adj_drop_graphs(lb_adj* a)
+{
+    for (auto& kv : a->seg_graphs) (void)hipGraphExecDestroy(kv.second);
+    a->seg_graphs.clear();
+}
+
+// One full segment of the backward pass from the state in buf[0] at t0:
+// the taped re-step of its n steps, then its n adjoint steps starting from
+// adjoint buffer `cur`.
+hipError_t adj_segment(lb_adj* a, int64_t t0, int64_t n, int cur)
+{
+    lb_ctx* c = a->fwd;
+    const size_t entry = (size_t)4 * c->p.nx * c->p.ny * (a->ap.f64 ? 8 : 4);
+    c->cur = 0;
+    c->t = t0;
+    for (int64_t j = 0; j < n; ++j) {
+        c->coef.step = (uint32_t)c->t;
+        hipError_t e = lbk::launch_step(c->p.storage, lbk::MODE_STEP_TAPE, c->buf[c->cur],
+                                        c->buf[c->cur ^ 1], c->g, c->coef,
+                                        reinterpret_cast<double*>(a->tape + j * entry), c->stream);
+        if (e) return e;
+        c->cur ^= 1;
+        ++c->t;
+    }
+    for (int64_t j = n - 1; j >= 0; --j) {
+        hipError_t e = lbk::adj_step(a->ap, a->lam[cur], a->g[cur], a->tape + j * entry,
+                                     a->lam[cur ^ 1], a->g[cur ^ 1], a->gF, a->part, c->stream);
+        if (e) return e;
+        cur ^= 1;
+    }
+    return hipSuccess;
+}
+
+// adj_segment as one replay of a captured graph where the stream allows
+// capture, else launch by launch.
+hipError_t adj_segment_graph(lb_adj* a, int64_t t0, int64_t n, int cur)
+{
+    lb_ctx* c = a->fwd;
+    if (a->use_graphs && (a->graph_G1 != a->ap.G1 || a->graph_G2 != a->ap.G2)) {
+        adj_drop_graphs(a);
+        a->graph_G1 = a->ap.G1;
+        a->graph_G2 = a->ap.G2;
+    }
+    if (!a->use_graphs) return adj_segment(a, t0, n, cur);
+    auto it = a->seg_graphs.find(cur);
+    if (it == a->seg_graphs.end()) {
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            const hipError_t le = adj_segment(a, t0, n, cur);
+            e = hipStreamEndCapture(c->stream, &graph);
+            if (e == hipSuccess && le != hipSuccess) e = le;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+            // This stream cannot be captured: launch by launch from now on.
+            (void)hipGetLastError();
+            a->use_graphs = false;
+            return adj_segment(a, t0, n, cur);
+        }
+        it = a->seg_graphs.emplace(cur, exec).first;
+    }
+    const hipError_t e = hipGraphLaunch(it->second, c->stream);
+    c->cur = (int)(n & 1);
+    c->t = t0 + n;
+    return e;
 }
 
 int check_adj(lb_adj* a)
@@ -1387,6 +1463,9 @@ int lb_adj_init(lb_adj** out, const lb_params* p, int64_t nsteps, int32_t checkp
     a->blocks = L.blocks;
     a->tape_seg = -1;
     a->have_forward = false;
+    a->graph_G1 = a->ap.G1;
+    a->graph_G2 = a->ap.G2;
+    a->use_graphs = hip_stream != nullptr;
     {
         std::lock_guard<std::mutex> lk(g_mu);
         g_adjs.insert(a);
@@ -1501,8 +1580,20 @@ int lb_adj_backward(lb_adj* a, double dG[2], double* drho, int on_device)
     for (int32_t s = a->nseg - 1; s >= 0; --s) {
         const int64_t t0 = (int64_t)s * a->every;
         const int64_t n = a->T - t0 < a->every ? a->T - t0 : a->every;
-        // Recompute the segment from its checkpoint, taping each state
-        // (unless the tape region still holds this segment).
+        // A full segment whose tape is not in place: restore its checkpoint
+        // and replay the captured taped re-step and adjoint steps.
+        if (a->tape_seg != s && n == a->every) {
+            a->tape_seg = -1;
+            if ((e = hipMemcpyAsync(c->buf[0], a->ckpt + (size_t)s * align_up(a->ckpt_bytes),
+                                    a->ckpt_bytes, hipMemcpyDeviceToDevice, st)))
+                return hip_fail(e, "checkpoint restore");
+            if ((e = adj_segment_graph(a, t0, n, cur))) return hip_fail(e, "adjoint segment");
+            a->tape_seg = s;
+            cur ^= (int)(n & 1);
+            continue;
+        }
+        // Otherwise recompute the segment from its checkpoint, taping each
+        // state (unless the tape region still holds this segment).
         if (a->tape_seg != s) {
             a->tape_seg = -1;
             if ((e = hipMemcpyAsync(c->buf[c->cur], a->ckpt + (size_t)s * align_up(a->ckpt_bytes),
@@ -1544,7 +1635,8 @@ int lb_adj_destroy(lb_adj* a)
         if (!a || !g_adjs.count(a)) return fail(LB_ERR_STATE, "unknown or destroyed adjoint context");
         g_adjs.erase(a);
     }
-    const int rc = lb_destroy(a->fwd);
+    const int rc = lb_destroy(a->fwd);  // synchronises the stream first
+    adj_drop_graphs(a);
     delete a;
     return rc;
 }

@@ -88,6 +88,32 @@ def test_backward_is_repeatable_and_device_input():
     dl.close()
 
 
+@pytest.mark.parametrize("every", [10, 7])
+def test_graph_replay_matches_launches(every):
+    # On a stream of its own the backward pass replays each full segment
+    # from a captured graph (even and odd segment lengths: one or two
+    # graphs); on the null stream it launches kernel by kernel.  Same bits,
+    # also after the couplings change (the graphs are captured again).
+    G1, G2 = inputs.couplings(0.1)
+    rho = inputs.rho_noise(40, 36, 6)
+    res = []
+    for side_stream in (False, True):
+        s = torch.cuda.Stream() if side_stream else torch.cuda.current_stream()
+        with torch.cuda.stream(s):
+            dl = DropletLoss(40, 36, 45, E_target=-500.0, beta=0.1, storage="f64",
+                             checkpoint_every=every)
+            out = []
+            for g1 in (G1, G1 * 1.01, G1):
+                L = dl.forward(rho, g1, G2)
+                dG1, dG2, drho = dl.backward()
+                out.append((L, dG1, dG2, drho.cpu().numpy()))
+            dl.close()
+        res.append(out)
+    for a, b in zip(*res):
+        assert a[0] == b[0] and (a[1], a[2]) == (b[1], b[2]) and np.array_equal(a[3], b[3])
+    assert res[1][0][1] == res[1][2][1]
+
+
 def test_autograd_function():
     G1, G2 = inputs.couplings(0.1)
     rho = torch.tensor(inputs.rho_noise(32, 32, 4), device="cuda", requires_grad=True)

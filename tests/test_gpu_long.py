@@ -1,0 +1,72 @@
+"""GPU: the 2048^2 single-precision workload over its full length.
+
+The 2048 x 2048 periodic lattice (r = 0.1 at A1 = -4.9, seed 1, tau = 1) is
+run for all 20000 steps in the library's default launch configuration (plain
+steps two per launch), with the section V observables logged every 500
+steps, and compared at every log point with the trace of the FP64 oracle
+stored in tests/golden/ (written by tests/golden/make_long_trace.py, which
+calls only the oracle; about 1.5 hours of CPU).  The same file holds the
+trace of the oracle's FP32 twin, whose deviation from FP64 sizes the
+single-precision bounds: the energy and sum psi^2 rows within three times
+the twin's largest relative deviation over the run.  The mass is held
+tighter than the twin's (the GPU takes the rest population from exact mass
+conservation, which the twin does not).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1008_2865_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if not torch.cuda.is_available():
+    pytest.skip("no HIP device", allow_module_level=True)
+
+from paper_1008_2865_amd import binding as B  # noqa: E402
+from paper_1008_2865_amd.sim import LBSim  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                      "trace_2048_r0.1_seed1_20000.txt")
+
+
+def load_golden():
+    rows = {"f64": [], "f32": []}
+    with open(GOLDEN) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, *vals = line.split()
+            rows[name].append([float(v) for v in vals])
+    return np.array(rows["f64"]), np.array(rows["f32"])
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden trace not generated")
+def test_full_length_trace_against_oracle():
+    f64, f32 = load_golden()
+    assert f64.shape == f32.shape == (41, 6)
+    G1, G2 = inputs.couplings(0.1)
+    sim = LBSim(inputs.rho_noise(2048, 2048, 1), G1=G1, G2=G2, storage="f32", log_every=500,
+                max_steps=20000)
+    assert B.lb_two_step_shape(sim.p)[0] > 0  # the default: plain steps two per launch
+    for _ in range(40):
+        sim.step(500)
+    tr = sim.trace()
+    sim.close()
+    assert tr.shape == (41, 6) and np.array_equal(tr[:, 0], f64[:, 0])
+
+    def rel(a, ref):
+        return np.abs(a - ref) / np.abs(ref)
+
+    E, E64, E32 = tr[:, 2] + tr[:, 3], f64[:, 2] + f64[:, 3], f32[:, 2] + f32[:, 3]
+    dE, dE_twin = rel(E, E64), rel(E32, E64)
+    dP, dP_twin = rel(tr[:, 4], f64[:, 4]), rel(f32[:, 4], f64[:, 4])
+    dM, dM_twin = rel(tr[:, 1], f64[:, 1]), rel(f32[:, 1], f64[:, 1])
+    print(f"20000 steps, 2048^2 FP32: max |dE/E| {dE.max():.2e} (twin {dE_twin.max():.2e}), "
+          f"max |d sum psi^2| {dP.max():.2e} (twin {dP_twin.max():.2e}), "
+          f"max |dM/M| {dM.max():.2e} (twin {dM_twin.max():.2e})", flush=True)
+    assert dE.max() <= 3 * dE_twin.max()
+    assert dP.max() <= 3 * dP_twin.max()
+    assert dM.max() <= dM_twin.max()

@@ -722,8 +722,11 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
     const int nrows = y1 - y0;
     const int nx = g.nx, ny = g.ny;
     auto modn = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
-    // Lattice row of walk row r (r runs from -5 to nrows + 5).
-    auto wrow = [&](int r) { return modn(ystart + r * dir, ny); };
+    // Lattice row of walk row r.  r runs from -5 to nrows + 4, so
+    // ystart + r dir lies in [y0 - 5, y1 + 4], within [-ny, 2 ny) for
+    // ny >= 5: one conditional add or subtract wraps it (a modulo by a
+    // value unknown at compile time costs a long scalar sequence per row).
+    auto wrow = [&](int r) { return wrapi(ystart + r * dir, ny); };
 
     const S* pl[9];
     S* pd[9];

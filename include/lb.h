@@ -80,10 +80,11 @@ typedef struct lb_params {
     int32_t tile_rows;   /* rows a workgroup updates per pipeline stage:
                             0 (library choice), 1 or 2                           */
     int32_t steps_per_launch; /* 0 (library choice: two per launch for LB_F32
-                            on large lattices), 1, or 2: with 2 the plain
-                            steps of LB_F32 and LB_F16DEV storage between log
-                            points run two per launch (temporal blocking); the
-                            fields are bit-identical to one step per launch    */
+                            and LB_F16DEV on large lattices), 1, or 2: with 2
+                            the plain steps of LB_F32 and LB_F16DEV storage
+                            between log points run two per launch (temporal
+                            blocking); the fields are bit-identical to one
+                            step per launch                                    */
     int64_t trace_cap;   /* rows the trace can hold (>= 0)                       */
     double tau;          /* BGK relaxation time, > 0.5 (the paper uses 1)        */
     double rho0;         /* psi scale, > 0 (the paper fixes rho0 = 1)            */

@@ -228,17 +228,17 @@ Geom make_geom2(const lb_params& p, const Geom& g)
 }
 
 // Whether plain steps run two per launch: FP32 or half storage when asked
-// for (steps_per_launch = 2); by default FP32 storage on lattices large
-// enough for tiles of 8 rows or more (below that the one-step kernel is as
-// fast or faster: 1024^2 16.6 us/step either way, 512^2 11.7 against 7.7).
-// Half storage stays at one step per launch by default: its step moves half
-// the bytes and is bound by arithmetic, not memory, so the two-step kernel
-// gains nothing there (8192^2: 0.599 against 0.600 ms/step).
+// for (steps_per_launch = 2), and by default on lattices large enough for
+// tiles of 8 rows or more (below that the one-step kernel is as fast or
+// faster: FP32 1024^2 16.6 us/step either way, 512^2 11.7 against 7.7;
+// half storage 1024^2 18.1 against 15.5).  Half storage, two per launch
+// against one: 2048^2 41.1 against 48.1 us/step, 4096^2 152.8 against
+// 166.3, 8192^2 551 against 627.
 bool use_two(const lb_params& p, const Geom& g2)
 {
     if (p.storage != LB_F32 && p.storage != LB_F16DEV) return false;
     if (p.steps_per_launch == 2) return true;
-    return p.storage == LB_F32 && p.steps_per_launch == 0 && g2.tile_y >= 8;
+    return p.steps_per_launch == 0 && g2.tile_y >= 8;
 }
 
 // Workspace layout, each region 256-byte aligned.
@@ -806,10 +806,10 @@ int batch_layout(const lb_params* ps, int32_t count, BatchLayout* L)
             return fail(LB_ERR_INVALID, "too many tiles in the batch");
         L->tiles += g.blocks;
     }
-    // Two steps per launch: FP32 by default when the batch as a whole fills
-    // tiles of >= 16 rows (the tallest of 48, 32, 24, 16 rows giving >= 1400
-    // workgroups of 128 lanes; the lattices of a batch are narrow, so the
-    // tiles stay 128 lanes wide), half storage when asked for.
+    // Two steps per launch: FP32 or half storage, by default when the batch
+    // as a whole fills tiles of >= 16 rows (the tallest of 48, 32, 24, 16
+    // rows giving >= 1400 workgroups of 128 lanes; the lattices of a batch
+    // are narrow, so the tiles stay 128 lanes wide).
     const int spl = ps[0].steps_per_launch;
     int tile_y2 = 0;
     for (int r : {48, 32, 24, 16}) {
@@ -821,8 +821,7 @@ int batch_layout(const lb_params* ps, int32_t count, BatchLayout* L)
         }
     }
     const int st = ps[0].storage;
-    L->two = (st == LB_F32 && (spl == 2 || (spl == 0 && tile_y2 >= 16))) ||
-             (st == LB_F16DEV && spl == 2);
+    L->two = (st == LB_F32 || st == LB_F16DEV) && (spl == 2 || (spl == 0 && tile_y2 >= 16));
     if (L->two && tile_y2 == 0) tile_y2 = 8;
     L->tile_y2 = L->two ? tile_y2 : 0;
     L->tiles2 = 0;

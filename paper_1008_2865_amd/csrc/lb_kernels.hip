@@ -774,11 +774,17 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
         if (lane < kHpw) ring[slot][mlds] = ps;
     };
 
-    // Level-1 walk row p lives in Bf[(p + 3) % 4] (p >= -3); the level-2
-    // pre-collision row formed at iteration it in F2[(it + 2) % 4].
-    C Bf[4][9] = {};
-    C Hh[4] = {};
-    C F2[4][9] = {};
+    // Level-1 walk row p lives in Bf[(p + 3) % NBF] (p >= -3); the level-2
+    // pre-collision row formed at iteration it in F2[(it + 2) % NBF].  The
+    // loads of a row are issued LEAD iterations before its psi is staged:
+    // one for single precision; two for the half storage, whose loop then
+    // unrolls five-fold and, as compiled, needs fewer registers (165
+    // against 173: three waves per SIMD instead of two).
+    constexpr int LEAD = P::kDev ? 2 : 1;
+    constexpr int NBF = 3 + LEAD;
+    C Bf[NBF][9] = {};
+    C Hh[NBF] = {};
+    C F2[NBF][9] = {};
 
     // Prologue: psi at t of walk rows -5 .. -1 into ring slots 0 .. 4 and
     // the populations of rows -3 .. -1 into Bf[0 .. 2].
@@ -796,18 +802,24 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
         for (int r = 0; r < 3; ++r) ring[r + 2][tid + 2] = psi_of(density(Bf[r]), k);
 #pragma unroll
         for (int r = 0; r < 5; ++r) halo_psi(hv[r], r);
+        // Rows 0 .. LEAD - 2: their loads stay in flight into the walk.
+#pragma unroll
+        for (int r = 0; r < LEAD - 1; ++r) {
+            pull<P>(pl, g, xc, xcm, xcp, wrow(r), o, Bf[3 + r]);
+            Hh[3 + r] = halo_load(wrow(r));
+        }
     }
 
     // One iteration per level-1 row p = it - 3, it = 0 .. nrows + 6.
     auto group = [&](auto Jc, int it, int s0) {
-        constexpr int J = decltype(Jc)::value;  // it % 4
+        constexpr int J = decltype(Jc)::value;  // it % NBF
         const int p = it - 3;
-        // Lead row p + 3 (psi at t is needed up to row nrows + 4).
+        // Lead row p + 2 + LEAD (psi at t is needed up to row nrows + 4).
         {
-            const int r = p + 3;
+            const int r = p + 2 + LEAD;
             const int yl = r < nrows + 5 ? wrow(r) : wrow(p);
-            pull<P>(pl, g, xc, xcm, xcp, yl, o, Bf[(J + 3) % 4]);
-            Hh[(J + 3) % 4] = halo_load(yl);
+            pull<P>(pl, g, xc, xcm, xcp, yl, o, Bf[(J + 2 + LEAD) % NBF]);
+            Hh[(J + 2 + LEAD) % NBF] = halo_load(yl);
         }
         __syncthreads();
 
@@ -815,7 +827,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
         // (pulled from the ring rows p-3 .. p-1) and their psi.
         if (p >= 0) {
             // Formed here, collided two iterations later (which reads F2[J]).
-            C(&Fr)[9] = F2[(J + 2) % 4];
+            C(&Fr)[9] = F2[(J + 2) % NBF];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 // f_i(x, t+1) = f*_i(x - c_i): lattice row y - c_y is walk
@@ -838,7 +850,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             const Stencil<C> st(ring[slot(-2)], ring[slot(-1)], ring[slot(0)], ring[slot(1)],
                                 ring[slot(2)], tid + 2);
             C q[9];
-            site_collide<false, P::kDev>(Bf[J % 4], st, k, q, (C*)nullptr);
+            site_collide<false, P::kDev>(Bf[J % NBF], st, k, q, (C*)nullptr);
             S* lp[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) lp[i] = &fs[(p + 4) & 3][i][0];
@@ -847,10 +859,10 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             anchor = q[1];
         }
 
-        // Stage psi at t of the lead row p + 3.
+        // Stage psi at t of row p + 3.
         {
-            C(&NFr)[9] = Bf[(J + 3) % 4];
-            C& HF = Hh[(J + 3) % 4];
+            C(&NFr)[9] = Bf[(J + 3) % NBF];
+            C& HF = Hh[(J + 3) % NBF];
 #pragma unroll
             for (int i = 0; i < 9; ++i) asm volatile("" : "+v"(NFr[i]) : "v"(anchor));
             asm volatile("" : "+v"(HF) : "v"(anchor));
@@ -876,7 +888,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             const C* r_p2 = ring2[dir > 0 ? s2(2) : s2(-2)];
             const Stencil<C> st2(r_m2, r_m1, r_c, r_p1, r_p2, tid + 2);
             C q2[9];
-            site_collide<false, P::kDev>(F2[J % 4], st2, k2, q2, (C*)nullptr);
+            site_collide<false, P::kDev>(F2[J % NBF], st2, k2, q2, (C*)nullptr);
             if (own2) {
                 const int yq = wrow(qr);
                 const int xq = x0 + tid - 3;
@@ -903,6 +915,11 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
         group(Ic<3>{}, it, s0);
         s0 = step_slot(s0);
         if (++it >= iters) break;
+        if constexpr (NBF > 4) {
+            group(Ic<4>{}, it, s0);
+            s0 = step_slot(s0);
+            if (++it >= iters) break;
+        }
     }
 }
 

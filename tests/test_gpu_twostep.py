@@ -101,3 +101,6 @@ def test_two_step_residency_matches_the_occupancy_query():
     assert B.lb_two_step_shape(p) == (128, 23, 1530)
     p = B.make_params(3000, 3000, storage=B.LB_F32, G1=-5.4, G2=0.54)
     assert B.lb_two_step_shape(p)[:2] == (256, 47)
+    # The half storage's kernel has the same occupancy (three waves per SIMD).
+    p = B.make_params(2048, 2048, storage=B.LB_F16DEV, G1=-5.4, G2=0.54, rho_ref=0.7)
+    assert B.lb_two_step_shape(p) == (128, 23, 1530)

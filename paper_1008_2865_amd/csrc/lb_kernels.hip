@@ -54,8 +54,9 @@ struct PF32 {
 };
 // Half-precision deviation from the rest-state equilibrium w_i rho_ref.
 // Decoding is one rounding of off + h and encoding one rounding of v - off
-// followed by the conversion, in every kernel and at every call site: with
-// contraction allowed the compiler could fuse the product w_i * rho_ref
+// followed by the conversion (the step's collision forms the deviation
+// itself, at tau = 1 as one fma), in every kernel and at every call site:
+// with contraction allowed the compiler could fuse the product w_i * rho_ref
 // that forms the offset into the add, in some inlined copies and not in
 // others, and the same stored value would decode to neighbouring floats.
 struct PF16 {
@@ -194,21 +195,22 @@ __device__ __forceinline__ _Float16 half_stochastic_hw(float v, uint32_t r)
 // site sum to its density up to a single rounding) and is itself rounded
 // stochastically: at a uniform state every site would otherwise make the
 // same rounding error at every step and the total mass would drift.  For
-// the half storage q[0] is the density (site_collide<..., true>).
+// the half storage q[0] is the density and q[1..8] are already the
+// deviations f*_i - w_i rho_ref (site_collide<..., true>).
 template <class P>
 __device__ __forceinline__ void store_site(typename P::S* const* pd, int at,
                                            const typename P::C q[9],
                                            const Offs<P>& o, uint32_t rnd)
 {
     if constexpr (P::kDev) {
-        // q[0] holds rho.  The rest population is stored as what the rounded
-        // moving populations leave of rho, so the nine decoded values sum to
-        // rho up to the rounding of the rest itself.
+        // The rest population is stored as what the rounded moving
+        // populations leave of rho, so the nine decoded values sum to rho up
+        // to the rounding of the rest itself.
 #pragma clang fp contract(off)
         float resid = q[0] - o.osum;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const _Float16 h = (_Float16)(q[i] - o.of(i));
+            const _Float16 h = (_Float16)q[i];
             resid = __builtin_fmaf(-(float)h, (float)o.one, resid);  // exact product: resid - h
             pd[i][at] = h;
         }
@@ -298,11 +300,14 @@ struct Stencil {
 
 // Force of eq. (FORCE) and the velocity-shift BGK collision at one site: R
 // the pre-collision populations, st the psi stencil around the site, Q the
-// post-collision populations; with kTape also the tape entry.  Every kernel
-// that updates a site calls this, so all of them round identically.
-template <bool kTape, bool kRestIsRho, typename C>
+// post-collision populations; with kTape also the tape entry.  For the half
+// storage (kDev) Q[0] is the density and Q[1..8] the deviations
+// f*_i - w_i rho_ref from the offsets o1 (axis) and o2 (diagonal), which at
+// tau = 1 come out of one fma each.  Every kernel that updates a site calls
+// this, so all of them round identically.
+template <bool kTape, bool kDev, typename C>
 __device__ __forceinline__ void site_collide(const C (&R)[9], const Stencil<C>& st, const CoefT<C>& k,
-                                             C (&Q)[9], C* tp)
+                                             C (&Q)[9], C* tp, C o1 = (C)0, C o2 = (C)0)
 {
 #pragma clang fp contract(off)
     // Multiply-adds are written out as fma and nothing else is contracted,
@@ -347,26 +352,28 @@ __device__ __forceinline__ void site_collide(const C (&R)[9], const Stencil<C>& 
     const C base = fma_c((C)-1.5, fma_c(ux, ux, uy * uy), (C)1);
     const C r1 = rho * ((C)1 / (C)9);
     const C r2 = rho * ((C)1 / (C)36);
-    auto feq = [&](C r, C cu) { return r * fma_c(cu, fma_c((C)4.5, cu, (C)3), base); };
-    Q[1] = feq(r1, ux);
-    Q[2] = feq(r1, uy);
-    Q[3] = feq(r1, -ux);
-    Q[4] = feq(r1, -uy);
-    Q[5] = feq(r2, ux + uy);
-    Q[6] = feq(r2, uy - ux);
-    Q[7] = feq(r2, -ux - uy);
-    Q[8] = feq(r2, ux - uy);
+    auto poly = [&](C cu) { return fma_c(cu, fma_c((C)4.5, cu, (C)3), base); };
+    const C pr[9] = {(C)0,        poly(ux),       poly(uy),        poly(-ux), poly(-uy),
+                     poly(ux + uy), poly(uy - ux), poly(-ux - uy), poly(ux - uy)};
+    auto wr = [&](int i) { return i < 5 ? r1 : r2; };
+    auto off = [&](int i) { return i < 5 ? o1 : o2; };
     // f* = f + (f_eq - f) / tau; at tau = 1 (every run of the paper) that is
     // f_eq itself.  The branch is uniform.
     if (k.omega != (C)1) {
         const C om = k.omega;
 #pragma unroll
-        for (int i = 1; i < 9; ++i) Q[i] = fma_c(om, Q[i] - R[i], R[i]);
+        for (int i = 1; i < 9; ++i) {
+            Q[i] = fma_c(om, wr(i) * pr[i] - R[i], R[i]);
+            if (kDev) Q[i] = Q[i] - off(i);
+        }
+    } else {
+#pragma unroll
+        for (int i = 1; i < 9; ++i) Q[i] = kDev ? fma_c(wr(i), pr[i], -off(i)) : wr(i) * pr[i];
     }
     // The collision conserves mass exactly; the rest population is taken
     // from that, so rounding cannot drift the mass.  The half storage forms
     // it when it rounds the moving populations: there Q[0] carries rho.
-    if (kRestIsRho)
+    if (kDev)
         Q[0] = rho;
     else
         Q[0] = rho - (((Q[1] + Q[3]) + (Q[2] + Q[4])) + ((Q[5] + Q[7]) + (Q[6] + Q[8])));
@@ -585,7 +592,7 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
             }
 
             if (kCollide) {
-                site_collide<kTape, P::kDev>(R, st, k, q[m], tp[m]);
+                site_collide<kTape, P::kDev>(R, st, k, q[m], tp[m], o.o1, o.o2);
                 if (m == 0) anchor = q[m][1];
             } else if (m == 0) {
                 anchor = p;
@@ -850,7 +857,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             const Stencil<C> st(ring[slot(-2)], ring[slot(-1)], ring[slot(0)], ring[slot(1)],
                                 ring[slot(2)], tid + 2);
             C q[9];
-            site_collide<false, P::kDev>(Bf[J % NBF], st, k, q, (C*)nullptr);
+            site_collide<false, P::kDev>(Bf[J % NBF], st, k, q, (C*)nullptr, o.o1, o.o2);
             S* lp[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) lp[i] = &fs[(p + 4) & 3][i][0];
@@ -888,7 +895,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             const C* r_p2 = ring2[dir > 0 ? s2(2) : s2(-2)];
             const Stencil<C> st2(r_m2, r_m1, r_c, r_p1, r_p2, tid + 2);
             C q2[9];
-            site_collide<false, P::kDev>(F2[J % NBF], st2, k2, q2, (C*)nullptr);
+            site_collide<false, P::kDev>(F2[J % NBF], st2, k2, q2, (C*)nullptr, o.o1, o.o2);
             if (own2) {
                 const int yq = wrow(qr);
                 const int xq = x0 + tid - 3;

@@ -783,10 +783,11 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
 
     // Level-1 walk row p lives in Bf[(p + 3) % NBF] (p >= -3); the level-2
     // pre-collision row formed at iteration it in F2[(it + 2) % NBF].  The
-    // loads of a row are issued LEAD iterations before its psi is staged:
+    // loads of a row are written LEAD iterations before its psi is staged:
     // one for single precision; two for the half storage, whose loop then
-    // unrolls five-fold and, as compiled, needs fewer registers (165
-    // against 173: three waves per SIMD instead of two).
+    // unrolls five-fold.  The compiler moves those loads back next to their
+    // use (the source is read-only), and for the five-fold loop it needs
+    // fewer registers (165 against 173: three waves per SIMD, not two).
     constexpr int LEAD = P::kDev ? 2 : 1;
     constexpr int NBF = 3 + LEAD;
     C Bf[NBF][9] = {};

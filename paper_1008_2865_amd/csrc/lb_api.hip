@@ -184,6 +184,10 @@ int64_t step2_slots(int storage, int tile_x)
 //   66.7 (115.7);  3000^2 256x47 81.3, 256x48 83.0, 128x48 108.6 (151.9);
 //   4096^2 256x46 150.0, 256x48 151.0 (243.9);  8192^2 256x45 589.6,
 //   256x48 604.6, 128x48 658.4 (1037.9).
+// Half storage, whose two-step kernel is not bound by memory, takes 56
+// rows once a launch spans four rounds or more: 8192^2 (us per launch)
+// 256x56 895, 256x60 899, 256x51 904, 256x45 917; at 4096^2 (two rounds)
+// 256x46 251 against 256x56 260.
 Geom make_geom2(const lb_params& p, const Geom& g)
 {
     Geom g2 = g;
@@ -214,7 +218,10 @@ Geom make_geom2(const lb_params& p, const Geom& g)
                 const int64_t rounds = (strips(tx) * rows(48) + slots - 1) / slots;
                 const int64_t per_strip = rounds * slots / strips(tx);
                 const int fit = per_strip > 0 ? (int)((p.ny + per_strip - 1) / per_strip) : 48;
-                if (fit >= 44 && fit < 48) ty = fit;
+                if (p.storage == LB_F16DEV && rounds >= 4)
+                    ty = 56;  // fewer halo rows pay more than a full last round
+                else if (fit >= 44 && fit < 48)
+                    ty = fit;
             }
         }
     }

@@ -225,9 +225,10 @@ def test_default_launch_shape(n, shape):
     (2048, P.LB_F32, 1, (0, 0, 0)),
     (1024, P.LB_F16DEV, 0, (0, 0, 0)),
     (2048, P.LB_F16DEV, 0, (128, 23, 1530)),  # half storage: the same rule
-    (8192, P.LB_F16DEV, 0, (256, 45, 6039)),
+    (4096, P.LB_F16DEV, 0, (256, 46, 1530)),
+    (8192, P.LB_F16DEV, 0, (256, 56, 4851)),  # many rounds: taller tiles
     (8192, P.LB_F16DEV, 1, (0, 0, 0)),
-    (8192, P.LB_F16DEV, 2, (256, 45, 6039)),
+    (8192, P.LB_F16DEV, 2, (256, 56, 4851)),
     (2048, P.LB_F64, 2, (0, 0, 0))])         # no double-precision two-step kernel
 def test_two_step_default_shape(n, storage, spl, shape):
     p = good(nx=n, ny=n, storage=storage, steps_per_launch=spl, rho_ref=0.7)

@@ -692,11 +692,14 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
 // order); its post-collision rows go to a 4-row LDS ring instead of memory.
 // Level 2 trails it: at walk row p it pulls the pre-collision populations of
 // row p-2 at t+1 from that ring (rows p-3 .. p-1, lanes l-1 .. l+1), stages
-// their psi, and, after a second barrier, applies the same force and
+// their psi, and, after the row's barrier, applies the same force and
 // collision (site_collide, so every site rounds as in two one-step
-// launches) to row p-4, which it stores.  Global traffic per two steps is
-// one read and one write of the populations, plus halo rows and columns that
-// neighbouring tiles also read.
+// launches) to row p-4, which it stores.  One barrier per walk row: every
+// LDS row an iteration reads was written before the previous barrier, and
+// the slots written between two barriers are not read between them (the
+// rings are deep enough).  Global traffic per two steps is one read and one
+// write of the populations, plus halo rows and columns that neighbouring
+// tiles also read.
 // ---------------------------------------------------------------------------
 template <class P, int NT>
 __device__ __forceinline__ void
@@ -817,6 +820,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             Hh[3 + r] = halo_load(wrow(r));
         }
     }
+    __syncthreads();
 
     // One iteration per level-1 row p = it - 3, it = 0 .. nrows + 6.
     auto group = [&](auto Jc, int it, int s0) {
@@ -829,7 +833,6 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             pull<P>(pl, g, xc, xcm, xcp, yl, o, Bf[(J + 2 + LEAD) % NBF]);
             Hh[(J + 2 + LEAD) % NBF] = halo_load(yl);
         }
-        __syncthreads();
 
         // Level 2, part 1: pre-collision populations at t+1 of row p - 2
         // (pulled from the ring rows p-3 .. p-1) and their psi.

@@ -14,6 +14,7 @@ HIP events on the library's stream), and the CPU oracle timed on a bounded
 sample of the same workload.
 """
 import argparse
+import glob
 import hashlib
 import json
 import os
@@ -26,9 +27,7 @@ sys.path.insert(0, ROOT)
 PEAK_HBM_GBPS = 8000.0
 BYTES_PER_LU = {"f64": 144, "f32": 72, "f16dev": 36}
 METRIC = "MLUPS and achieved HBM GB/s (two-belt D2Q9 step); adjoint/forward time ratio"
-TRAFFIC_FILES = [os.path.join(ROOT, "profiles", "k_step2_f32_2048_traffic.txt"),
-                 os.path.join(ROOT, "profiles", "k_step_f32_2048_traffic.txt"),
-                 os.path.join(ROOT, "profiles", "k_step2_batch_96_f32_traffic.txt")]
+TRAFFIC_FILES = sorted(glob.glob(os.path.join(ROOT, "profiles", "*_traffic.txt")))
 KERNEL_SRC = os.path.join(ROOT, "paper_1008_2865_amd", "csrc", "lb_kernels.hip")
 
 

@@ -826,6 +826,14 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
     auto group = [&](auto Jc, int it, int s0) {
         constexpr int J = decltype(Jc)::value;  // it % NBF
         const int p = it - 3;
+        // ring2 holds walk row r in slot (r + 12) % RS2.  s0 = it % RS,
+        // so walk row p - 6 + k sits in slot b2 + k (mod RS2), k = 0 .. 4,
+        // with no division.
+        const int b2 = s0 >= 3 ? s0 - 3 : s0 + 3;
+        auto slot2 = [&](int kk) {
+            const int v = b2 + kk;
+            return v >= RS2 ? v - RS2 : v;
+        };
         // Lead row p + 2 + LEAD (psi at t is needed up to row nrows + 4).
         {
             const int r = p + 2 + LEAD;
@@ -848,7 +856,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
                 const int li = min(max(tid - q_cx(i), 0), NT - 1);
                 Fr[i] = o.ld(&fs[(rr + 4) & 3][i][li], o.of(i));
             }
-            ring2[(p - 2 + 12) % RS2][tid + 2] = psi_of(density(Fr), k2);
+            ring2[slot2(4)][tid + 2] = psi_of(density(Fr), k2);
         }
 
         // Level 1: force and collision of row p into the ring of t+1.
@@ -889,14 +897,13 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
         // psi rows q-2 .. q+2 at t+1; store.
         const int qr = p - 4;
         if (qr >= 0 && qr < nrows) {
-            auto s2 = [&](int dy) { return (qr + dy + 12) % RS2; };
-            // Walk rows are in walk order; psi row qr + dy is lattice row
-            // ystart + (qr + dy) dir, i.e. the stencil's y + dy dir.
-            const C* r_m2 = ring2[dir > 0 ? s2(-2) : s2(2)];
-            const C* r_m1 = ring2[dir > 0 ? s2(-1) : s2(1)];
-            const C* r_c = ring2[s2(0)];
-            const C* r_p1 = ring2[dir > 0 ? s2(1) : s2(-1)];
-            const C* r_p2 = ring2[dir > 0 ? s2(2) : s2(-2)];
+            // Walk rows are in walk order; psi row qr + dy (slot2(2 + dy)) is
+            // lattice row ystart + (qr + dy) dir, i.e. the stencil's y + dy dir.
+            const C* r_m2 = ring2[slot2(2 - 2 * dir)];
+            const C* r_m1 = ring2[slot2(2 - dir)];
+            const C* r_c = ring2[slot2(2)];
+            const C* r_p1 = ring2[slot2(2 + dir)];
+            const C* r_p2 = ring2[slot2(2 + 2 * dir)];
             const Stencil<C> st2(r_m2, r_m1, r_c, r_p1, r_p2, tid + 2);
             C q2[9];
             site_collide<false, P::kDev>(F2[J % NBF], st2, k2, q2, (C*)nullptr, o.o1, o.o2);

@@ -71,7 +71,9 @@ struct PF16 {
     __device__ static void st(S* p, C v, C off)
     {
 #pragma clang fp contract(off)
-        *p = (S)(v - off);
+        C d = v - off;
+        asm("" : "+v"(d));  // round d, then convert (never one fused rounding)
+        *p = (S)d;
     }
 };
 
@@ -210,7 +212,13 @@ __device__ __forceinline__ void store_site(typename P::S* const* pd, int at,
         float resid = q[0] - o.osum;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
-            const _Float16 h = (_Float16)q[i];
+            // Round the single-precision value, not the exact result of the
+            // operation that formed it: the compiler may otherwise fuse that
+            // fma with the conversion into one mixed-precision instruction
+            // (a single rounding), in some kernels and not in others.
+            float v = q[i];
+            asm("" : "+v"(v));
+            const _Float16 h = (_Float16)v;
             resid = __builtin_fmaf(-(float)h, (float)o.one, resid);  // exact product: resid - h
             pd[i][at] = h;
         }
@@ -303,9 +311,11 @@ struct Stencil {
 // post-collision populations; with kTape also the tape entry.  For the half
 // storage (kDev) Q[0] is the density and Q[1..8] the deviations
 // f*_i - w_i rho_ref from the offsets o1 (axis) and o2 (diagonal), which at
-// tau = 1 come out of one fma each.  Every kernel that updates a site calls
-// this, so all of them round identically.
-template <bool kTape, bool kDev, typename C>
+// tau = 1 come out of one fma each.  kOm = 1 or 0 states that tau is 1, or
+// is not, for a caller that has branched on it already; -1 tests k.omega.
+// Every kernel that updates a site calls this, so all of them round
+// identically.
+template <bool kTape, bool kDev, int kOm = -1, typename C>
 __device__ __forceinline__ void site_collide(const C (&R)[9], const Stencil<C>& st, const CoefT<C>& k,
                                              C (&Q)[9], C* tp, C o1 = (C)0, C o2 = (C)0)
 {
@@ -359,7 +369,7 @@ __device__ __forceinline__ void site_collide(const C (&R)[9], const Stencil<C>& 
     auto off = [&](int i) { return i < 5 ? o1 : o2; };
     // f* = f + (f_eq - f) / tau; at tau = 1 (every run of the paper) that is
     // f_eq itself.  The branch is uniform.
-    if (k.omega != (C)1) {
+    if (kOm == 0 || (kOm < 0 && k.omega != (C)1)) {
         const C om = k.omega;
 #pragma unroll
         for (int i = 1; i < 9; ++i) {
@@ -701,10 +711,22 @@ step_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst
 // write of the populations, plus halo rows and columns that neighbouring
 // tiles also read.
 // ---------------------------------------------------------------------------
+// LDS of a two-step workgroup, declared once per kernel so that the walks
+// for tau = 1 and for other tau share it.
 template <class P, int NT>
+struct Step2Smem {
+    static constexpr int RS = 6, RS2 = 6, NF = 4;
+    typename P::C ring[RS][NT + 4];   // psi at t, level-1 rows p-2 .. p+3
+    typename P::C ring2[RS2][NT + 4]; // psi at t+1, rows p-7 .. p-2
+    // Post-collision populations of step t+1, in the storage type and
+    // rounded exactly as a one-step launch stores them.
+    typename P::S fs[NF][9][NT];
+};
+
+template <class P, int NT, int kOm>
 __device__ __forceinline__ void
 step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst,
-           const Geom& g, const CoefT<typename P::C>& k, const int lb)
+           const Geom& g, const CoefT<typename P::C>& k, const int lb, Step2Smem<P, NT>& sm)
 {
     using S = typename P::S;
     using C = typename P::C;
@@ -712,12 +734,10 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
     constexpr int LW = NT + 4;          // psi rings: lanes plus 2 columns each side
     constexpr int kWaves = NT / 64;
     constexpr int kHpw = 4 / kWaves;
-    constexpr int RS = 6, RS2 = 6, NF = 4;
-    __shared__ C ring[RS][LW];          // psi at t, level-1 rows p-2 .. p+3
-    __shared__ C ring2[RS2][LW];        // psi at t+1, rows p-7 .. p-2
-    // Post-collision populations of step t+1, in the storage type and
-    // rounded exactly as a one-step launch stores them.
-    __shared__ S fs[NF][9][NT];
+    constexpr int RS = Step2Smem<P, NT>::RS, RS2 = Step2Smem<P, NT>::RS2, NF = Step2Smem<P, NT>::NF;
+    C (&ring)[RS][LW] = sm.ring;
+    C (&ring2)[RS2][LW] = sm.ring2;
+    S (&fs)[NF][9][NT] = sm.fs;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -869,7 +889,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             const Stencil<C> st(ring[slot(-2)], ring[slot(-1)], ring[slot(0)], ring[slot(1)],
                                 ring[slot(2)], tid + 2);
             C q[9];
-            site_collide<false, P::kDev>(Bf[J % NBF], st, k, q, (C*)nullptr, o.o1, o.o2);
+            site_collide<false, P::kDev, kOm>(Bf[J % NBF], st, k, q, (C*)nullptr, o.o1, o.o2);
             S* lp[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) lp[i] = &fs[(p + 4) & 3][i][0];
@@ -906,7 +926,7 @@ step2_tile(const typename P::S* __restrict__ src, typename P::S* __restrict__ ds
             const C* r_p2 = ring2[slot2(2 + 2 * dir)];
             const Stencil<C> st2(r_m2, r_m1, r_c, r_p1, r_p2, tid + 2);
             C q2[9];
-            site_collide<false, P::kDev>(F2[J % NBF], st2, k2, q2, (C*)nullptr, o.o1, o.o2);
+            site_collide<false, P::kDev, kOm>(F2[J % NBF], st2, k2, q2, (C*)nullptr, o.o1, o.o2);
             if (own2) {
                 const int yq = wrow(qr);
                 const int xq = x0 + tid - 3;
@@ -946,7 +966,13 @@ __global__ void __launch_bounds__(NT)
 k_step2(const typename P::S* __restrict__ src, typename P::S* __restrict__ dst, Geom g,
         CoefT<typename P::C> k)
 {
-    step2_tile<P, NT>(src, dst, g, k, xcd_remap(blockIdx.x, gridDim.x));
+    // tau = 1 (every run of the paper) and other tau as separate walks, so
+    // the collision has no branch inside the loop.
+    __shared__ Step2Smem<P, NT> sm;
+    if (k.omega == (typename P::C)1)
+        step2_tile<P, NT, 1>(src, dst, g, k, xcd_remap(blockIdx.x, gridDim.x), sm);
+    else
+        step2_tile<P, NT, 0>(src, dst, g, k, xcd_remap(blockIdx.x, gridDim.x), sm);
 }
 
 // One launch = one time step of one lattice: workgroup b updates logical
@@ -978,8 +1004,13 @@ k_step2_batch(const BatchLattice* __restrict__ desc, const int32_t* __restrict__
     const float* cf = d.coef_f;
     const CoefT<float> k{cf[0], cf[1], cf[2],  cf[3],  cf[4],  cf[5], cf[6],
                          cf[7], cf[8], cf[9], cf[10], cf[11], cf[12], step};
-    step2_tile<P, NT>(static_cast<const S*>(d.buf[parity]), static_cast<S*>(d.buf[parity ^ 1]),
-                      d.geom2, k, gl - d.tile_begin2);
+    __shared__ Step2Smem<P, NT> sm;  // tau = 1 and other tau as separate walks
+    if (k.omega == 1.0f)
+        step2_tile<P, NT, 1>(static_cast<const S*>(d.buf[parity]), static_cast<S*>(d.buf[parity ^ 1]),
+                             d.geom2, k, gl - d.tile_begin2, sm);
+    else
+        step2_tile<P, NT, 0>(static_cast<const S*>(d.buf[parity]), static_cast<S*>(d.buf[parity ^ 1]),
+                             d.geom2, k, gl - d.tile_begin2, sm);
 }
 
 template <class P, int NT, int MODE, int RPI, int LEAD>

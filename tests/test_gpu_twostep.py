@@ -57,6 +57,18 @@ def test_two_steps_per_launch_bit_identical(nx, ny, tile_x, tile_y, storage):
 
 
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])
+@pytest.mark.parametrize("tau", [0.8, 1.3])
+def test_two_steps_per_launch_bit_identical_other_tau(storage, tau):
+    # The relaxation f + (f_eq - f) / tau with tau != 1 (the paper's runs
+    # use tau = 1, which takes the collision's other path).
+    rho0 = inputs.rho_noise(150, 60, 8)
+    a, _ = run(rho0, 41, 1, storage=storage, tau=tau, tile_x=128, tile_y=16)
+    b, _ = run(rho0, 41, 2, storage=storage, tau=tau, tile_x=128, tile_y=16)
+    bits = np.uint32 if storage == "f32" else np.uint16
+    assert np.array_equal(a.view(bits), b.view(bits))
+
+
+@pytest.mark.parametrize("storage", ["f32", "f16dev"])
 def test_logging_and_chunks(storage):
     rho0 = inputs.rho_noise(96, 80, 7)
     a, ta = run(rho0, 100, 1, storage=storage, log_every=7, tile_y=16)

@@ -260,7 +260,8 @@ int lb_batch_destroy(lb_batch* b);
  * the backward pass recomputes each segment from its copy, recording
  * (rho, j, psi) of every state, and steps the adjoint back through it.
  * Storage must be LB_F64 or LB_F32 (the arithmetic precision of both
- * passes; global sums in double); log_every and trace_cap are ignored.
+ * passes; global sums in double); nx * ny <= 2^29 (LB_ERR_INVALID beyond);
+ * log_every and trace_cap are ignored.
  * Workspace and stream rules are those of lb_init.
  * ------------------------------------------------------------------------ */
 typedef struct lb_adj lb_adj;

@@ -68,6 +68,41 @@ __device__ __forceinline__ int wrapn(int v, int n)
     return v >= n ? v - n : v;
 }
 
+// Site s of the dense [ny][nx] arrays with the offsets of rows y-2 .. y+2
+// and the columns x-2 .. x+2, wrapped periodically, so that the element of
+// neighbour (dx, dy) is at(dx, dy).  Element offsets fit in 32 bits and
+// byte offsets too (the host limits an adjoint lattice to 2^29 sites).
+struct Nbhd {
+    int x, y, ro[5], cx[5];
+    __device__ __forceinline__ Nbhd(int s, int nx, int ny)
+    {
+        const int N = nx * ny;
+        y = (int)((unsigned)s / (unsigned)nx);
+        x = s - y * nx;
+        ro[2] = s - x;
+        ro[3] = ro[2] + nx;
+        ro[3] = ro[3] >= N ? ro[3] - N : ro[3];
+        ro[4] = ro[3] + nx;
+        ro[4] = ro[4] >= N ? ro[4] - N : ro[4];
+        ro[1] = ro[2] - nx;
+        ro[1] = ro[1] < 0 ? ro[1] + N : ro[1];
+        ro[0] = ro[1] - nx;
+        ro[0] = ro[0] < 0 ? ro[0] + N : ro[0];
+#pragma unroll
+        for (int k = 0; k < 5; ++k) cx[k] = wrapn(x + k - 2, nx);
+    }
+    __device__ __forceinline__ int at(int dx, int dy) const { return ro[dy + 2] + cx[dx + 2]; }
+};
+
+// base[e] with the byte offset formed in 32 bits (a uniform base plus a
+// per-lane 32-bit offset, which needs no 64-bit address arithmetic).
+template <typename T>
+__device__ __forceinline__ T ld32(const T* base, int e)
+{
+    const uint32_t b = (uint32_t)e * (uint32_t)sizeof(T);
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + b);
+}
+
 __device__ __forceinline__ double ex(double v) { return exp(v); }
 __device__ __forceinline__ float ex(float v) { return expf(v); }
 __device__ __forceinline__ double sq(double v) { return sqrt(v); }
@@ -135,22 +170,23 @@ __global__ void __launch_bounds__(kThreads)
 k_adj_a(const C* __restrict__ lam_next, const C* __restrict__ g_next, const C* __restrict__ tape,
         AdjArgs<C> a, C* __restrict__ lam, C* __restrict__ gF, double* __restrict__ part)
 {
-    const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int s = blockIdx.x * kThreads + threadIdx.x;
     double dg[2] = {0.0, 0.0};
     if (s < a.N) {
-        const int x = (int)(s % a.nx), y = (int)(s / a.nx);
+        const Nbhd nb(s, a.nx, a.ny);
         const C* psi = tape + 3 * a.N;
         C mu[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            const int64_t n = (int64_t)wrapn(y + kQy[i], a.ny) * a.nx + wrapn(x + kQx[i], a.nx);
-            mu[i] = lam_next[i * a.N + n] + g_next[n];
+            const int n = nb.at(kQx[i], kQy[i]);
+            mu[i] = ld32(lam_next + i * a.N, n) + ld32(g_next, n);
         }
-        const C rho = tape[s], jx = tape[a.N + s], jy = tape[2 * a.N + s], p = psi[s];
+        const C rho = ld32(tape, s), jx = ld32(tape + a.N, s), jy = ld32(tape + 2 * a.N, s),
+                p = ld32(psi, s);
         C s1x = 0, s1y = 0, s2x = 0, s2y = 0;
 #pragma unroll
         for (int k = 0; k < 24; ++k) {
-            const C pn = psi[(int64_t)wrapn(y + kLy[k], a.ny) * a.nx + wrapn(x + kLx[k], a.nx)];
+            const C pn = ld32(psi, nb.at(kLx[k], kLy[k]));
             if (k < 8) {
                 s1x += (C)(kLw[k] * kLx[k]) * pn;
                 s1y += (C)(kLw[k] * kLy[k]) * pn;
@@ -190,20 +226,21 @@ template <typename C>
 __global__ void __launch_bounds__(kThreads)
 k_adj_b(const C* __restrict__ tape, const C* __restrict__ gF, AdjArgs<C> a, C* __restrict__ g)
 {
-    const int64_t s = (int64_t)blockIdx.x * kThreads + threadIdx.x;
+    const int s = blockIdx.x * kThreads + threadIdx.x;
     if (s >= a.N) return;
-    const int x = (int)(s % a.nx), y = (int)(s / a.nx);
+    const Nbhd nb(s, a.nx, a.ny);
     const C* psi = tape + 3 * a.N;
-    const C gx = gF[s], gy = gF[a.N + s];
+    const C* gFy = gF + a.N;
+    const C gx = ld32(gF, s), gy = ld32(gFy, s);
     C acc = 0;
 #pragma unroll
     for (int k = 0; k < 24; ++k) {
-        const int64_t n = (int64_t)wrapn(y + kLy[k], a.ny) * a.nx + wrapn(x + kLx[k], a.nx);
+        const int n = nb.at(kLx[k], kLy[k]);
         const C Kk = a.G1 * (C)kLw[k] + a.G2 * (C)kLp[k];
-        acc += Kk * psi[n] * ((gx - gF[n]) * (C)kLx[k] + (gy - gF[a.N + n]) * (C)kLy[k]);
+        acc += Kk * ld32(psi, n) * ((gx - ld32(gF, n)) * (C)kLx[k] + (gy - ld32(gFy, n)) * (C)kLy[k]);
     }
     // psi' = exp(-rho/rho0) sqrt(rho0)/rho0 = (sqrt(rho0) - psi)/rho0.
-    g[s] = -acc * ((a.sqrt_rho0 - psi[s]) * a.inv_rho0);
+    g[s] = -acc * ((a.sqrt_rho0 - ld32(psi, s)) * a.inv_rho0);
 }
 
 // Interface measure: a(x) = sqrt(Dx^2 + Dy^2 + eps^2) from central

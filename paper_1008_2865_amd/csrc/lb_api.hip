@@ -1382,6 +1382,11 @@ int adj_layout(const lb_params* p, int64_t nsteps, int32_t every, AdjLayout* L)
         return fail(LB_ERR_INVALID, "the adjoint needs LB_F64 or LB_F32 storage");
     if (nsteps < 0) return fail(LB_ERR_INVALID, "nsteps must be >= 0");
     if (every < 1) return fail(LB_ERR_INVALID, "checkpoint_every must be >= 1");
+    // The adjoint kernels address their dense per-site arrays with 32-bit
+    // byte offsets from a per-array base (8-byte values).
+    if ((int64_t)p->nx * p->ny > (int64_t(1) << 29))
+        return fail(LB_ERR_INVALID, "the adjoint supports at most 2^29 sites (got %lld)",
+                    (long long)p->nx * p->ny);
     L->fp = *p;
     L->fp.log_every = 0;
     L->fp.trace_cap = 0;

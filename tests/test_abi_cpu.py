@@ -171,8 +171,10 @@ def test_adjoint_host_validation():
     assert B.lb_adj_workspace_bytes(p, 600, 100) > nb         # more checkpoints
     assert B.lb_adj_workspace_bytes(p, 0, 1) > 0               # T = 0 is valid
     for bad in [(B.make_params(64, 48, storage=P.LB_F16DEV), 10, 5),
-                (p, -1, 5), (p, 10, 0), (B.make_params(4, 48), 10, 5)]:
+                (p, -1, 5), (p, 10, 0), (B.make_params(4, 48), 10, 5),
+                (B.make_params(32768, 32768, storage=P.LB_F32), 10, 5)]:  # > 2^29 sites
         assert B.lb_adj_workspace_bytes(*bad) == 0
+    assert B.lb_adj_workspace_bytes(B.make_params(16384, 32768, storage=P.LB_F32), 10, 5) > 0
     for fn, args in [(B.lb_adj_backward, (np.zeros((48, 64)),)), (B.lb_adj_destroy, ()),
                      (B.lb_adj_forward, (np.full((48, 64), 0.7), -5.0, 0.5, 0.0, 0.0, 1e-6))]:
         with pytest.raises(B.LBError) as e:

@@ -274,12 +274,17 @@ typedef struct lb_adj_loss {
 
 /* Workspace bytes for T = nsteps >= 0 steps with a checkpoint every
  * checkpoint_every >= 1 steps (about ceil(T/every) population copies plus
- * `every` tape entries of 4 values per site), or 0 if invalid. */
+ * two regions of `every` tape entries of 4 values per site: the backward
+ * pass re-steps the next segment into one while it reads the other), or 0
+ * if invalid. */
 size_t lb_adj_workspace_bytes(const lb_params* p, int64_t nsteps,
                               int32_t checkpoint_every);
 
 /* Create an adjoint context.  p's tau, rho0, sizes, storage and launch
- * shape are used; G1 and G2 are given to each lb_adj_forward. */
+ * shape are used; G1 and G2 are given to each lb_adj_forward.  With a
+ * stream (not the null stream) the context also creates a stream of its
+ * own, at the default priority, for the backward pass's re-steps, which it
+ * orders against hip_stream with events and destroys in lb_adj_destroy. */
 int lb_adj_init(lb_adj** out, const lb_params* p, int64_t nsteps,
                 int32_t checkpoint_every, void* workspace, size_t bytes,
                 void* hip_stream);

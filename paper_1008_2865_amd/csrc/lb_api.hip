@@ -14,6 +14,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <set>
@@ -1244,7 +1245,7 @@ struct lb_adj {
     int32_t every, nseg;
     size_t ckpt_bytes;    // one raw population buffer
     char* ckpt;           // nseg checkpoints, at t = 0, every, 2 every, ...
-    char* tape;           // `every` tape entries of 4 N values
+    char* tapes[2];       // two regions of `every` tape entries of 4 N values
     char* tapeT;          // tape entry of the state at T
     char* lam[2];         // 9 N values each
     char* g[2];           // N values each
@@ -1256,13 +1257,22 @@ struct lb_adj {
     double* red;          // 8 reduced values
     double* drho;         // N doubles
     int blocks;
-    int32_t tape_seg;     // segment whose tape the tape region holds, or -1
+    int32_t tape_of[2];   // segment whose tape each region holds, or -1
     bool have_forward;
     double E, A, E_target, beta, eps;
-    // Full backward segments replay a captured graph (keyed by the parity of
-    // the adjoint buffers at its start), valid for the couplings it was
-    // captured with.
-    std::map<int, hipGraphExec_t> seg_graphs;
+    // The backward pass re-steps segment s - 1 (taping it into region
+    // (s - 1) & 1) on `side` while the adjoint steps of segment s run on
+    // the context's stream; ev_r[b] marks region b taped, ev_a[b] region b
+    // read.  Without a stream of its own (the null stream) both run in turn
+    // on the context's stream.
+    hipStream_t side;
+    bool own_side;
+    hipEvent_t ev_r[2], ev_a[2];
+    // Full segments replay captured graphs: the taped re-step keyed by its
+    // region, the adjoint steps by region and the parity of the adjoint
+    // buffers at their start; valid for the couplings they were captured
+    // with.
+    std::map<int, hipGraphExec_t> tape_graphs, adj_graphs;
     double graph_G1, graph_G2;
     bool use_graphs;
 };
@@ -1271,9 +1281,9 @@ namespace {
 
 std::set<lb_adj*> g_adjs;
 
-// n steps of the forward lattice, each also recording the tape entry of
-// the state it leaves (entry j = state t + j).
-int adj_tape_steps(lb_adj* a, int64_t n)
+// n steps of the forward lattice on stream st, each also recording the tape
+// entry of the state it leaves (entry j = state t + j) in `tape`.
+hipError_t adj_tape_steps(lb_adj* a, int64_t n, char* tape, hipStream_t st)
 {
     lb_ctx* c = a->fwd;
     const size_t entry = (size_t)4 * c->p.nx * c->p.ny * (a->ap.f64 ? 8 : 4);
@@ -1281,66 +1291,50 @@ int adj_tape_steps(lb_adj* a, int64_t n)
         c->coef.step = (uint32_t)c->t;
         hipError_t e = lbk::launch_step(c->p.storage, lbk::MODE_STEP_TAPE, c->buf[c->cur],
                                         c->buf[c->cur ^ 1], c->g, c->coef,
-                                        reinterpret_cast<double*>(a->tape + j * entry), c->stream);
-        if (e) return hip_fail(e, "step kernel launch");
-        c->cur ^= 1;
-        ++c->t;
-    }
-    return LB_OK;
-}
-
-void adj_drop_graphs(lb_adj* a)
-{
-    for (auto& kv : a->seg_graphs) (void)hipGraphExecDestroy(kv.second);
-    a->seg_graphs.clear();
-}
-
-// One full segment of the backward pass from the state in buf[0] at t0:
-// the taped re-step of its n steps, then its n adjoint steps starting from
-// adjoint buffer `cur`.
-hipError_t adj_segment(lb_adj* a, int64_t t0, int64_t n, int cur)
-{
-    lb_ctx* c = a->fwd;
-    const size_t entry = (size_t)4 * c->p.nx * c->p.ny * (a->ap.f64 ? 8 : 4);
-    c->cur = 0;
-    c->t = t0;
-    for (int64_t j = 0; j < n; ++j) {
-        c->coef.step = (uint32_t)c->t;
-        hipError_t e = lbk::launch_step(c->p.storage, lbk::MODE_STEP_TAPE, c->buf[c->cur],
-                                        c->buf[c->cur ^ 1], c->g, c->coef,
-                                        reinterpret_cast<double*>(a->tape + j * entry), c->stream);
+                                        reinterpret_cast<double*>(tape + j * entry), st);
         if (e) return e;
         c->cur ^= 1;
         ++c->t;
     }
+    return hipSuccess;
+}
+
+// n adjoint steps on stream st, from tape entry n - 1 down to 0, starting
+// from adjoint buffer `cur`.
+hipError_t adj_back_steps(lb_adj* a, int64_t n, const char* tape, int cur, hipStream_t st)
+{
+    const size_t entry = (size_t)4 * a->ap.nx * a->ap.ny * (a->ap.f64 ? 8 : 4);
     for (int64_t j = n - 1; j >= 0; --j) {
-        hipError_t e = lbk::adj_step(a->ap, a->lam[cur], a->g[cur], a->tape + j * entry,
-                                     a->lam[cur ^ 1], a->g[cur ^ 1], a->gF, a->part, c->stream);
+        hipError_t e = lbk::adj_step(a->ap, a->lam[cur], a->g[cur], tape + j * entry,
+                                     a->lam[cur ^ 1], a->g[cur ^ 1], a->gF, a->part, st);
         if (e) return e;
         cur ^= 1;
     }
     return hipSuccess;
 }
 
-// adj_segment as one replay of a captured graph where the stream allows
-// capture, else launch by launch.
-hipError_t adj_segment_graph(lb_adj* a, int64_t t0, int64_t n, int cur)
+void adj_drop_graphs(lb_adj* a)
 {
-    lb_ctx* c = a->fwd;
-    if (a->use_graphs && (a->graph_G1 != a->ap.G1 || a->graph_G2 != a->ap.G2)) {
-        adj_drop_graphs(a);
-        a->graph_G1 = a->ap.G1;
-        a->graph_G2 = a->ap.G2;
-    }
-    if (!a->use_graphs) return adj_segment(a, t0, n, cur);
-    auto it = a->seg_graphs.find(cur);
-    if (it == a->seg_graphs.end()) {
+    for (auto& kv : a->tape_graphs) (void)hipGraphExecDestroy(kv.second);
+    for (auto& kv : a->adj_graphs) (void)hipGraphExecDestroy(kv.second);
+    a->tape_graphs.clear();
+    a->adj_graphs.clear();
+}
+
+// Launch `work` on st, as one replay of a graph captured under `key` in
+// `graphs` when graphs are in use (captured on first use), else directly.
+hipError_t adj_replay(lb_adj* a, std::map<int, hipGraphExec_t>& graphs, int key, hipStream_t st,
+                      const std::function<hipError_t()>& work)
+{
+    if (!a->use_graphs) return work();
+    auto it = graphs.find(key);
+    if (it == graphs.end()) {
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
-        hipError_t e = hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal);
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
-            const hipError_t le = adj_segment(a, t0, n, cur);
-            e = hipStreamEndCapture(c->stream, &graph);
+            const hipError_t le = work();
+            e = hipStreamEndCapture(st, &graph);
             if (e == hipSuccess && le != hipSuccess) e = le;
         }
         if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1349,14 +1343,61 @@ hipError_t adj_segment_graph(lb_adj* a, int64_t t0, int64_t n, int cur)
             // This stream cannot be captured: launch by launch from now on.
             (void)hipGetLastError();
             a->use_graphs = false;
-            return adj_segment(a, t0, n, cur);
+            adj_drop_graphs(a);
+            return work();
         }
-        it = a->seg_graphs.emplace(cur, exec).first;
+        it = graphs.emplace(key, exec).first;
     }
-    const hipError_t e = hipGraphLaunch(it->second, c->stream);
-    c->cur = (int)(n & 1);
-    c->t = t0 + n;
-    return e;
+    return hipGraphLaunch(it->second, st);
+}
+
+// Tape segment s into region s & 1 on the side stream (unless the region
+// holds it already), once the adjoint steps that last read that region are
+// done; marks the region taped.
+hipError_t adj_restep(lb_adj* a, int32_t s)
+{
+    lb_ctx* c = a->fwd;
+    const int b = s & 1;
+    hipStream_t st = a->side;
+    hipError_t e;
+    if (a->tape_of[b] != s) {
+        a->tape_of[b] = -1;
+        const int64_t t0 = (int64_t)s * a->every;
+        const int64_t n = a->T - t0 < a->every ? a->T - t0 : a->every;
+        if ((e = hipStreamWaitEvent(st, a->ev_a[b], 0)) ||
+            (e = hipMemcpyAsync(c->buf[0], a->ckpt + (size_t)s * align_up(a->ckpt_bytes), a->ckpt_bytes,
+                                hipMemcpyDeviceToDevice, st)))
+            return e;
+        c->cur = 0;
+        c->t = t0;
+        auto work = [&] { return adj_tape_steps(a, n, a->tapes[b], st); };
+        if (n == a->every) {
+            e = adj_replay(a, a->tape_graphs, b, st, work);
+            c->cur = (int)(n & 1);
+            c->t = t0 + n;
+        } else {
+            e = work();
+        }
+        if (e) return e;
+        a->tape_of[b] = s;
+    }
+    return hipEventRecord(a->ev_r[b], st);
+}
+
+// The adjoint steps of segment s on the context's stream, once its tape is
+// in place; marks its region read.
+hipError_t adj_backseg(lb_adj* a, int32_t s, int cur)
+{
+    const int b = s & 1;
+    hipStream_t st = a->fwd->stream;
+    const int64_t t0 = (int64_t)s * a->every;
+    const int64_t n = a->T - t0 < a->every ? a->T - t0 : a->every;
+    hipError_t e;
+    if ((e = hipStreamWaitEvent(st, a->ev_r[b], 0))) return e;
+    auto work = [&] { return adj_back_steps(a, n, a->tapes[b], cur, st); };
+    e = n == a->every ? adj_replay(a, a->adj_graphs, b * 2 + cur, st, work) : work();
+    if (e) return e;
+    return hipEventRecord(a->ev_a[b], st);
 }
 
 int check_adj(lb_adj* a)
@@ -1368,7 +1409,7 @@ int check_adj(lb_adj* a)
 
 struct AdjLayout {
     lb_params fp;         // forward parameters: no trace
-    size_t fwd, fwd_bytes, ckpt, ckpt_bytes, tape, tapeT, lam[2], g[2], gF, dir, part, partE, partA,
+    size_t fwd, fwd_bytes, ckpt, ckpt_bytes, tape[2], tapeT, lam[2], g[2], gF, dir, part, partE, partA,
         red, drho, total;
     int32_t nseg;
     int blocks;
@@ -1403,7 +1444,7 @@ int adj_layout(const lb_params* p, int64_t nsteps, int32_t every, AdjLayout* L)
     L->fwd = off; L->fwd_bytes = F.total; off += align_up(F.total);
     L->ckpt_bytes = (size_t)9 * g.plane * es;
     L->ckpt = off; off += (size_t)nseg * align_up(L->ckpt_bytes);
-    L->tape = off; off += align_up((size_t)seg_len * 4 * N * es);
+    for (int q = 0; q < 2; ++q) { L->tape[q] = off; off += align_up((size_t)seg_len * 4 * N * es); }
     L->tapeT = off; off += align_up((size_t)4 * N * es);
     for (int q = 0; q < 2; ++q) { L->lam[q] = off; off += align_up((size_t)9 * N * es); }
     for (int q = 0; q < 2; ++q) { L->g[q] = off; off += align_up((size_t)N * es); }
@@ -1458,7 +1499,10 @@ int lb_adj_init(lb_adj** out, const lb_params* p, int64_t nsteps, int32_t checkp
     a->nseg = L.nseg;
     a->ckpt_bytes = L.ckpt_bytes;
     a->ckpt = ws + L.ckpt;
-    a->tape = ws + L.tape;
+    for (int q = 0; q < 2; ++q) {
+        a->tapes[q] = ws + L.tape[q];
+        a->tape_of[q] = -1;
+    }
     a->tapeT = ws + L.tapeT;
     for (int q = 0; q < 2; ++q) {
         a->lam[q] = ws + L.lam[q];
@@ -1472,11 +1516,32 @@ int lb_adj_init(lb_adj** out, const lb_params* p, int64_t nsteps, int32_t checkp
     a->red = reinterpret_cast<double*>(ws + L.red);
     a->drho = reinterpret_cast<double*>(ws + L.drho);
     a->blocks = L.blocks;
-    a->tape_seg = -1;
     a->have_forward = false;
     a->graph_G1 = a->ap.G1;
     a->graph_G2 = a->ap.G2;
     a->use_graphs = hip_stream != nullptr;
+    // The re-steps get a stream of their own (default priority) when the
+    // context has one; on the null stream everything runs in turn.
+    a->side = c->stream;
+    a->own_side = false;
+    a->ev_r[0] = a->ev_r[1] = a->ev_a[0] = a->ev_a[1] = nullptr;
+    {
+        DeviceGuard dg(c->device);
+        hipError_t e = dg.err;
+        for (hipEvent_t* ev : {&a->ev_r[0], &a->ev_r[1], &a->ev_a[0], &a->ev_a[1]})
+            if (!e) e = hipEventCreateWithFlags(ev, hipEventDisableTiming);
+        if (!e && hip_stream) {
+            e = hipStreamCreateWithFlags(&a->side, hipStreamNonBlocking);
+            a->own_side = e == hipSuccess;
+        }
+        if (e) {
+            for (hipEvent_t ev : {a->ev_r[0], a->ev_r[1], a->ev_a[0], a->ev_a[1]})
+                if (ev) (void)hipEventDestroy(ev);
+            delete a;
+            lb_destroy(c);
+            return hip_fail(e, "adjoint stream and events");
+        }
+    }
     {
         std::lock_guard<std::mutex> lk(g_mu);
         g_adjs.insert(a);
@@ -1517,7 +1582,10 @@ int lb_adj_forward(lb_adj* a, const double* rho_init, int on_device, double G1, 
         r = c->staging;
     }
     a->have_forward = false;
-    a->tape_seg = -1;
+    a->tape_of[0] = a->tape_of[1] = -1;
+    // Work left on the side stream by an earlier backward pass reads the
+    // lattice buffers this run overwrites.
+    if (a->own_side && (e = hipStreamSynchronize(a->side))) return hip_fail(e, "synchronise");
     c->p.G1 = G1;
     c->p.G2 = G2;
     c->coef = make_coef(c->p);
@@ -1538,8 +1606,8 @@ int lb_adj_forward(lb_adj* a, const double* rho_init, int on_device, double G1, 
         if (s + 1 < a->nseg) {
             if ((rc = lb_step(c, n))) return rc;
         } else {
-            if ((rc = adj_tape_steps(a, n))) return rc;
-            a->tape_seg = s;
+            if ((e = adj_tape_steps(a, n, a->tapes[s & 1], st))) return hip_fail(e, "step kernel launch");
+            a->tape_of[s & 1] = s;
         }
     }
     if ((e = lbk::adj_tape(c->p.storage, c->buf[c->cur], c->g, a->ap, a->tapeT, st)) ||
@@ -1578,8 +1646,6 @@ int lb_adj_backward(lb_adj* a, double dG[2], double* drho, int on_device)
     DeviceGuard dg(c->device);
     if (dg.err) return hip_fail(dg.err, "select device");
     const int64_t N = (int64_t)c->p.nx * c->p.ny;
-    const size_t es = a->ap.f64 ? 8 : 4;
-    const size_t entry = (size_t)4 * N * es;
     hipStream_t st = c->stream;
     const double two_dE = 2.0 * (a->E - a->E_target);
     hipError_t e;
@@ -1587,39 +1653,25 @@ int lb_adj_backward(lb_adj* a, double dG[2], double* drho, int on_device)
         (e = lbk::adj_seed(a->ap, a->tapeT, a->dir, two_dE, a->beta, a->lam[0], a->g[0], a->partE, st)) ||
         (e = lbk::adj_zero(a->part, (int64_t)a->blocks * 2, st)))
         return hip_fail(e, "adjoint seed");
+    if (a->use_graphs && (a->graph_G1 != a->ap.G1 || a->graph_G2 != a->ap.G2)) {
+        adj_drop_graphs(a);
+        a->graph_G1 = a->ap.G1;
+        a->graph_G2 = a->ap.G2;
+    }
+    // Segments from the last to the first: the adjoint steps of segment s
+    // (context stream) overlap the taped re-step of segment s - 1 (side
+    // stream).  Both regions start out free, and the side stream starts
+    // after the seed.
+    if ((e = hipEventRecord(a->ev_a[0], st)) || (e = hipEventRecord(a->ev_a[1], st)))
+        return hip_fail(e, "adjoint events");
+    if (a->nseg > 0 && (e = adj_restep(a, a->nseg - 1))) return hip_fail(e, "adjoint re-step");
     int cur = 0;
     for (int32_t s = a->nseg - 1; s >= 0; --s) {
+        if (s > 0 && (e = adj_restep(a, s - 1))) return hip_fail(e, "adjoint re-step");
+        if ((e = adj_backseg(a, s, cur))) return hip_fail(e, "adjoint steps");
         const int64_t t0 = (int64_t)s * a->every;
         const int64_t n = a->T - t0 < a->every ? a->T - t0 : a->every;
-        // A full segment whose tape is not in place: restore its checkpoint
-        // and replay the captured taped re-step and adjoint steps.
-        if (a->tape_seg != s && n == a->every) {
-            a->tape_seg = -1;
-            if ((e = hipMemcpyAsync(c->buf[0], a->ckpt + (size_t)s * align_up(a->ckpt_bytes),
-                                    a->ckpt_bytes, hipMemcpyDeviceToDevice, st)))
-                return hip_fail(e, "checkpoint restore");
-            if ((e = adj_segment_graph(a, t0, n, cur))) return hip_fail(e, "adjoint segment");
-            a->tape_seg = s;
-            cur ^= (int)(n & 1);
-            continue;
-        }
-        // Otherwise recompute the segment from its checkpoint, taping each
-        // state (unless the tape region still holds this segment).
-        if (a->tape_seg != s) {
-            a->tape_seg = -1;
-            if ((e = hipMemcpyAsync(c->buf[c->cur], a->ckpt + (size_t)s * align_up(a->ckpt_bytes),
-                                    a->ckpt_bytes, hipMemcpyDeviceToDevice, st)))
-                return hip_fail(e, "checkpoint restore");
-            c->t = t0;
-            if ((rc = adj_tape_steps(a, n))) return rc;
-            a->tape_seg = s;
-        }
-        for (int64_t j = n - 1; j >= 0; --j) {
-            if ((e = lbk::adj_step(a->ap, a->lam[cur], a->g[cur], a->tape + j * entry, a->lam[cur ^ 1],
-                                   a->g[cur ^ 1], a->gF, a->part, st)))
-                return hip_fail(e, "adjoint step");
-            cur ^= 1;
-        }
+        cur ^= (int)(n & 1);
     }
     double* dst = on_device ? drho : a->drho;
     if ((e = lbk::adj_rho_grad(a->ap, a->lam[cur], a->g[cur], dst, st)) ||
@@ -1646,8 +1698,11 @@ int lb_adj_destroy(lb_adj* a)
         if (!a || !g_adjs.count(a)) return fail(LB_ERR_STATE, "unknown or destroyed adjoint context");
         g_adjs.erase(a);
     }
+    if (a->own_side) (void)hipStreamSynchronize(a->side);
     const int rc = lb_destroy(a->fwd);  // synchronises the stream first
     adj_drop_graphs(a);
+    if (a->own_side) (void)hipStreamDestroy(a->side);
+    for (hipEvent_t ev : {a->ev_r[0], a->ev_r[1], a->ev_a[0], a->ev_a[1]}) (void)hipEventDestroy(ev);
     delete a;
     return rc;
 }

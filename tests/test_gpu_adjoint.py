@@ -76,16 +76,29 @@ def test_checkpoint_interval_does_not_change_gradients():
 
 
 def test_backward_is_repeatable_and_device_input():
+    # On the null stream (re-steps and adjoint steps in turn) and on a
+    # stream of its own (re-steps on a second stream, overlapping the
+    # adjoint steps): repeated backward passes, which re-step every segment
+    # again, give the same bits, and so do the two streams.
     G1, G2 = inputs.couplings(0.1)
     rho = inputs.rho_noise(64, 64, 2)
-    dl = DropletLoss(64, 64, 40, E_target=-900.0, beta=1.0 / 4096, storage="f32", checkpoint_every=16)
-    a = dl.forward(rho, G1, G2)
-    b = dl.forward(torch.tensor(rho, device="cuda"), G1, G2)
-    assert a == b
-    g1 = dl.backward()
-    g2 = dl.backward()
-    assert g1[:2] == g2[:2] and torch.equal(g1[2], g2[2])
-    dl.close()
+    grads = []
+    for own_stream in (False, True):
+        s = torch.cuda.Stream() if own_stream else torch.cuda.current_stream()
+        with torch.cuda.stream(s):
+            dl = DropletLoss(64, 64, 40, E_target=-900.0, beta=1.0 / 4096, storage="f32",
+                             checkpoint_every=16)
+            a = dl.forward(rho, G1, G2)
+            b = dl.forward(torch.tensor(rho, device="cuda"), G1, G2)
+            assert a == b
+            g1 = dl.backward()
+            g2 = dl.backward()
+            g3 = dl.backward()
+            dl.close()
+        for g in (g2, g3):
+            assert g1[:2] == g[:2] and torch.equal(g1[2], g[2])
+        grads.append(g1)
+    assert grads[0][:2] == grads[1][:2] and torch.equal(grads[0][2], grads[1][2])
 
 
 @pytest.mark.parametrize("every", [10, 7])

@@ -146,7 +146,8 @@ def adjoint_ratio(n, T, every, storage, r, seed, reps):
 
     G1, G2 = inputs.couplings(r)
     rho = inputs.rho_noise(n, n, seed)
-    # A stream of its own, so the backward pass replays captured segments.
+    # A stream of its own, so the backward pass replays captured segments
+    # and overlaps each segment's re-step with the adjoint steps before it.
     with torch.cuda.stream(torch.cuda.Stream()):
         dl = DropletLoss(n, n, T, E_target=0.0, beta=1.0 / n ** 2, eps=1e-6, storage=storage,
                          checkpoint_every=every)
@@ -172,8 +173,9 @@ def adjoint_ratio(n, T, every, storage, r, seed, reps):
             "config": f"{n}x{n} periodic two-belt D2Q9, r={r}, seed {seed}, {storage}, T={T}, "
                       f"checkpoint every {every}, L=(E(T)-1.01 E_ref)^2 + A(T)/{n}^2, "
                       f"best of {reps} (forward: T steps + checkpoints + loss; backward: "
-                      f"recomputed segments, tape, adjoint steps, gradients; full segments "
-                      f"replayed from captured HIP graphs)",
+                      f"recomputed segments, tape, adjoint steps, gradients; the re-step of "
+                      f"segment s-1 on a second stream while the adjoint steps of segment s run; "
+                      f"full segments replayed from captured HIP graphs)",
             "loss": [L, E, A, M], "dG": [dG1, dG2], "drho_l2": float(torch.linalg.norm(drho))}
 
 

@@ -90,7 +90,10 @@ typedef struct lb_params {
     double rho0;         /* psi scale, > 0 (the paper fixes rho0 = 1)            */
     double G1, G2;       /* first- and second-belt couplings, G < 0 attracts     */
     double rho_ref;      /* LB_F16DEV only: populations are stored as
-                            f_i - w_i rho_ref (use the mean initial density)     */
+                            f_i - w_i rho', rho' = rho_ref rounded to 20
+                            significant bits so that the offsets and their
+                            sum are exact in single precision (use the mean
+                            initial density)                                    */
 } lb_params;
 
 /* Bytes of device workspace a context with these parameters needs, or 0 if

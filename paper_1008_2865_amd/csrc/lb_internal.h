@@ -38,6 +38,23 @@ struct Geom {
 
 // Physical coefficients, in double; the launchers convert them to the
 // arithmetic precision of the storage.
+// Half storage: the populations are kept as deviations f_i - w_i rho' from
+// offsets built on one single-precision value a = rho'/9 (the axis offset):
+// a is rho_ref/9 rounded to 20 significant bits, so that the rest offset
+// 4a, the diagonal offset a/4 and the sum of all nine offsets, 9a, are
+// exact.  The encoder subtracts that sum from the density; were it rounded,
+// every site would gain the same rounding error at every step, a drift of
+// the total mass linear in time.
+__host__ __device__ inline float dev_axis_offset(float rho_ref)
+{
+    float v = rho_ref * (1.0f / 9.0f);
+    uint32_t u;
+    __builtin_memcpy(&u, &v, sizeof u);
+    u = (u + 8u) & ~15u;  // nearest value with the low 4 significand bits clear
+    __builtin_memcpy(&v, &u, sizeof v);
+    return v;
+}
+
 struct Coef {
     double K1, K2, K4, K5, K8;  // link coupling of each |c|^2 class (Table 1)
     double KE0;                 // rest coupling of E_s: G1 w_0 + G2 p_s0

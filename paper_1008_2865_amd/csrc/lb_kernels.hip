@@ -52,13 +52,12 @@ struct PF32 {
     __device__ static C ld(const S* p, C) { return *p; }
     __device__ static void st(S* p, C v, C) { *p = v; }
 };
-// Half-precision deviation from the rest-state equilibrium w_i rho_ref.
-// Decoding is one rounding of off + h and encoding one rounding of v - off
-// followed by the conversion (the step's collision forms the deviation
-// itself, at tau = 1 as one fma), in every kernel and at every call site:
-// with contraction allowed the compiler could fuse the product w_i * rho_ref
-// that forms the offset into the add, in some inlined copies and not in
-// others, and the same stored value would decode to neighbouring floats.
+// Half-precision deviation from the rest-state equilibrium w_i rho', rho'
+// within 2^-20 of rho_ref (the offsets of dev_axis_offset).  Decoding is one
+// rounding of off + h and encoding one rounding of v - off followed by the
+// conversion (the step's collision forms the deviation itself, at tau = 1
+// as one fma), in every kernel and at every call site, with contraction
+// off, so that the same stored value decodes to the same float everywhere.
 struct PF16 {
     using S = _Float16;
     using C = float;
@@ -141,7 +140,7 @@ __device__ __forceinline__ int xcd_remap(int b, int nb)
                      : rem * (per + 1) + (xcd - rem) * per + idx;
 }
 
-// Deviation offsets w_i rho_ref of the half storage (zero otherwise), and
+// Deviation offsets w_i rho' of the half storage (zero otherwise), and
 // the decoding of a stored value.
 template <class P>
 struct Offs {
@@ -153,12 +152,13 @@ struct Offs {
     __device__ Offs(C rho_ref)
     {
 #pragma clang fp contract(off)
-        // Each offset is the rounded product; no later add may absorb it.
-        if (P::kDev) {
-            o0 = rho_ref * ((C)4 / (C)9);
-            o1 = rho_ref * ((C)1 / (C)9);
-            o2 = rho_ref * ((C)1 / (C)36);
-            osum = (o0 + (C)4 * o1) + (C)4 * o2;
+        // Offsets and their sum exact in single precision (dev_axis_offset).
+        if constexpr (P::kDev) {
+            static_assert(sizeof(C) == 4, "the half storage computes in single precision");
+            o1 = dev_axis_offset(rho_ref);
+            o0 = (C)4 * o1;
+            o2 = (C)0.25 * o1;
+            osum = (C)9 * o1;
         } else {
             o0 = o1 = o2 = osum = (C)0;
         }

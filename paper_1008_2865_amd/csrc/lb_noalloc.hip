@@ -212,11 +212,11 @@ hipError_t na_run(const void* state, int nx, int ny, const Coef& c, const float*
         k.sqrt_rho0 = cf[8];
         k.inv_rho0 = cf[9];
         {
-#pragma clang fp contract(off)
-            const float rr = sizeof(S) == 2 ? cf[10] : 0.0f;
-            k.o0 = rr * (4.0f / 9.0f);
-            k.o1 = rr * (1.0f / 9.0f);
-            k.o2 = rr * (1.0f / 36.0f);
+            // The offsets of the step kernels (dev_axis_offset).
+            const float a = sizeof(S) == 2 ? dev_axis_offset(cf[10]) : 0.0f;
+            k.o1 = a;
+            k.o0 = 4.0f * a;
+            k.o2 = 0.25f * a;
         }
     }
     const int tiles = ((nx + kNaTx - 1) / kNaTx) * ((ny + kNaTy - 1) / kNaTy);

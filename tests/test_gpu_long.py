@@ -70,3 +70,29 @@ def test_full_length_trace_against_oracle():
     assert dE.max() <= 3 * dE_twin.max()
     assert dP.max() <= 3 * dP_twin.max()
     assert dM.max() <= dM_twin.max()
+
+
+@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden trace not generated")
+def test_half_storage_full_length_against_oracle():
+    # The same 20000-step run with populations stored as half-precision
+    # deviations (plain steps two per launch, the default for this storage
+    # on a lattice this size), against the FP64 oracle's trace: the
+    # precision form's global bounds, |dM/M| and |dE/E| <= 1e-3 at every
+    # log point (measured 2.2e-5 and 8.5e-5; with offsets whose sum was
+    # rounded the mass drifted linearly to 1.06e-3).
+    f64, _ = load_golden()
+    G1, G2 = inputs.couplings(0.1)
+    sim = LBSim(inputs.rho_noise(2048, 2048, 1), G1=G1, G2=G2, storage="f16dev", log_every=500,
+                max_steps=20000)
+    assert B.lb_two_step_shape(sim.p)[0] > 0
+    for _ in range(40):
+        sim.step(500)
+    tr = sim.trace()
+    sim.close()
+    assert tr.shape == (41, 6) and np.array_equal(tr[:, 0], f64[:, 0])
+    dM = np.abs(tr[:, 1] - f64[:, 1]) / f64[:, 1]
+    E, E64 = tr[:, 2] + tr[:, 3], f64[:, 2] + f64[:, 3]
+    dE = np.abs(E - E64) / np.abs(E64)
+    print(f"20000 steps, 2048^2 half storage: max |dE/E| {dE.max():.2e}, max |dM/M| {dM.max():.2e}",
+          flush=True)
+    assert dM.max() <= 1e-3 and dE.max() <= 1e-3

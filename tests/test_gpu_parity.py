@@ -337,8 +337,8 @@ def test_f16dev_error_is_bounded():
 def test_f16dev_precision_form_512():
     # The precision form on the 512x512 run (spinodal, r = 0.1, seed 1,
     # 5000 steps): pointwise fields decorrelate once interfaces form, so the
-    # stated errors are the global ones.  Measured on MI355X: dM/M ~ 4e-5,
-    # dE/E ~ 6e-5 (the stochastically rounded, mass-compensated rest
+    # stated errors are the global ones.  Measured on MI355X: dM/M ~ 3e-5,
+    # dE/E ~ 9e-5 (the stochastically rounded, mass-compensated rest
     # population keeps the mass from drifting; without it dM/M was -1.1e-2).
     # The same run with plain steps two per launch (the default for half
     # storage on larger lattices) must give the same bits over all 5000

@@ -177,23 +177,37 @@ int64_t step2_slots(int storage, int tile_x)
 // Two-step launch shape.  A workgroup walks its rows one after the other,
 // so while every tile is resident at once (one round), shorter tiles finish
 // sooner: the default takes the shortest tiles (128 lanes, else 256) that
-// all fit in one round, up to 48 rows; larger lattices take 256-lane tiles
-// of about 48 rows, a few rows shorter when that fills the last round.
+// all fit in one round, up to 48 rows.  Past that, a launch of more than
+// one round pays for a last round left partly empty, and a taller tile for
+// fewer recomputed halo rows:
+//   - single precision: 256-lane tiles filling one round when they are at
+//     most 96 rows tall, else tiles of about 48 rows, a few rows shorter
+//     when that fills the last round, or, when the last round would be
+//     under half full, the height that fills one round fewer (at most 56);
+//   - half storage, whose two-step kernel is not bound by memory: the
+//     tallest 256-lane tiles of at most 128 rows whose last round is full.
 // Measured on MI355X (FP32, us/step; one step per launch in brackets):
 //   1200^2 128x8 18.0 (20.0);  1800^2 128x18 30.0, 128x24 33.3 (43.0);
 //   2048^2 128x23 41.4, 128x24 42.1 (61.2);  2500^2 128x48 66.2, 128x40
 //   66.7 (115.7);  3000^2 256x47 81.3, 256x48 83.0, 128x48 108.6 (151.9);
-//   4096^2 256x46 150.0, 256x48 151.0 (243.9);  8192^2 256x45 589.6,
-//   256x48 604.6, 128x48 658.4 (1037.9).
-// Half storage, whose two-step kernel is not bound by memory, takes 56
-// rows once a launch spans four rounds or more: 8192^2 (us per launch)
-// 256x56 895, 256x60 899, 256x51 904, 256x45 917; at 4096^2 (two rounds)
-// 256x46 251 against 256x56 260.
+//   4096^2 256x92 144.0, 128x92 146.2, 256x46 147.5 (243.9);  5120^2
+//   256x47 227.7, 256x71 231.5, 256x143 233.7;  8192^2 256x45 589.6,
+//   256x48 604.6, 256x90 601.6, 256x179 619.7, 128x48 658.4 (1037.9).
+// Half storage, us per launch: 8192^2 256x119 840-848 (three rounds),
+// 256x90 847, 256x179 850, 256x357 860, 256x56 857-872 (6.3 rounds),
+// 256x104 883 (3.4 rounds), 256x164 907 (2.1 rounds); 4096^2 256x92 235,
+// 256x46 241-243, 256x56 248.
 Geom make_geom2(const lb_params& p, const Geom& g)
 {
     Geom g2 = g;
     auto strips = [&](int tx) { return (int64_t)(p.nx + tx - 7) / (tx - 6); };
     auto rows = [&](int ty) { return (int64_t)(p.ny + ty - 1) / ty; };
+    // Height of the tiles of tx lanes that fill nr rounds (their count is at
+    // most nr rounds' worth, and just under it).
+    auto fill = [&](int tx, int64_t nr) -> int64_t {
+        const int64_t per_strip = nr * step2_slots(p.storage, tx) / strips(tx);
+        return per_strip > 0 ? (p.ny + per_strip - 1) / per_strip : (int64_t)p.ny;
+    };
     int tx = p.tile_x, ty = p.tile_y;
     if (!tx || !ty) {
         int one_x = 0, one_y = 0;
@@ -214,15 +228,24 @@ Geom make_geom2(const lb_params& p, const Geom& g)
         } else {
             if (!tx) tx = 256;
             if (!ty) {
-                ty = 48;
-                const int64_t slots = step2_slots(p.storage, tx);
-                const int64_t rounds = (strips(tx) * rows(48) + slots - 1) / slots;
-                const int64_t per_strip = rounds * slots / strips(tx);
-                const int fit = per_strip > 0 ? (int)((p.ny + per_strip - 1) / per_strip) : 48;
-                if (p.storage == LB_F16DEV && rounds >= 4)
-                    ty = 56;  // fewer halo rows pay more than a full last round
-                else if (fit >= 44 && fit < 48)
-                    ty = fit;
+                if (p.storage == LB_F16DEV) {
+                    int64_t nr = 1;
+                    while (fill(tx, nr) > 128) ++nr;
+                    ty = (int)fill(tx, nr);
+                } else if (fill(tx, 1) <= 96) {
+                    ty = (int)fill(tx, 1);
+                } else {
+                    ty = 48;
+                    const int64_t slots = step2_slots(p.storage, tx);
+                    const int64_t tiles = strips(tx) * rows(48);
+                    const int64_t rounds = (tiles + slots - 1) / slots;
+                    const int64_t fit = fill(tx, rounds);
+                    if (fit >= 44 && fit < 48)
+                        ty = (int)fit;
+                    else if (rounds > 1 && 2 * (tiles - (rounds - 1) * slots) < slots &&
+                             fill(tx, rounds - 1) <= 56)
+                        ty = (int)fill(tx, rounds - 1);
+                }
             }
         }
     }

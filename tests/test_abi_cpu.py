@@ -222,15 +222,19 @@ def test_default_launch_shape(n, shape):
 @pytest.mark.parametrize("n,storage,spl,shape", [
     (1024, P.LB_F32, 0, (0, 0, 0)),          # tiles under 16 rows: one step per launch
     (2048, P.LB_F32, 0, (128, 23, 1530)),    # one round of resident 128-lane tiles
-    (4096, P.LB_F32, 0, (256, 46, 1530)),    # two rounds of 256-lane tiles
+    (3500, P.LB_F32, 0, (256, 65, 756)),     # one round of 256-lane tiles (<= 96 rows)
+    (4096, P.LB_F32, 0, (256, 92, 765)),
+    (5120, P.LB_F32, 0, (256, 47, 2289)),    # about 48 rows, the last round full
+    (6144, P.LB_F32, 0, (256, 51, 3025)),    # 48 rows would leave a 5th round 1/6 full
     (8192, P.LB_F32, 0, (256, 45, 6039)),
     (2048, P.LB_F32, 1, (0, 0, 0)),
     (1024, P.LB_F16DEV, 0, (0, 0, 0)),
-    (2048, P.LB_F16DEV, 0, (128, 23, 1530)),  # half storage: the same rule
-    (4096, P.LB_F16DEV, 0, (256, 46, 1530)),
-    (8192, P.LB_F16DEV, 0, (256, 56, 4851)),  # many rounds: taller tiles
+    (2048, P.LB_F16DEV, 0, (128, 23, 1530)),  # half storage: one round as FP32
+    (4096, P.LB_F16DEV, 0, (256, 92, 765)),
+    (6144, P.LB_F16DEV, 0, (256, 101, 1525)),  # tallest <= 128 rows filling its rounds
+    (8192, P.LB_F16DEV, 0, (256, 119, 2277)),  # three full rounds
     (8192, P.LB_F16DEV, 1, (0, 0, 0)),
-    (8192, P.LB_F16DEV, 2, (256, 56, 4851)),
+    (8192, P.LB_F16DEV, 2, (256, 119, 2277)),
     (2048, P.LB_F64, 2, (0, 0, 0))])         # no double-precision two-step kernel
 def test_two_step_default_shape(n, storage, spl, shape):
     p = good(nx=n, ny=n, storage=storage, steps_per_launch=spl, rho_ref=0.7)

@@ -278,7 +278,7 @@ def test_f16dev_full_size_launch_configuration():
     fo = oracle_f(rho0, 5, G1, G2)
     sim = gpu_run(rho0, 5, G1, G2, storage="f16dev", log_every=5)
     assert sim.launch_shape()[:3] == (256, 32, 1)
-    assert B.lb_two_step_shape(sim.p)[:2] == (256, 56)  # plain steps two per launch
+    assert B.lb_two_step_shape(sim.p)[:2] == (256, 119)  # plain steps two per launch
     rho, _, _ = sim.moments()
     assert dmax(rho, fo.sum(axis=0)) <= 2e-3
     tr = sim.trace()

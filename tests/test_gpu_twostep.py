@@ -45,6 +45,7 @@ def run(rho0, steps, spl, chunks=None, storage="f32", **kw):
     (7, 9, 64, 3),
     (257, 11, 256, 4),
     (64, 64, 128, 64),
+    (600, 300, 256, 119),  # the tall tiles of large half-storage lattices, ragged
 ])
 @pytest.mark.parametrize("storage", ["f32", "f16dev"])
 def test_two_steps_per_launch_bit_identical(nx, ny, tile_x, tile_y, storage):
@@ -116,3 +117,5 @@ def test_two_step_residency_matches_the_occupancy_query():
     # The half storage's kernel has the same occupancy (three waves per SIMD).
     p = B.make_params(2048, 2048, storage=B.LB_F16DEV, G1=-5.4, G2=0.54, rho_ref=0.7)
     assert B.lb_two_step_shape(p) == (128, 23, 1530)
+    p = B.make_params(8192, 8192, storage=B.LB_F16DEV, G1=-5.4, G2=0.54, rho_ref=0.7)
+    assert B.lb_two_step_shape(p) == (256, 119, 2277)

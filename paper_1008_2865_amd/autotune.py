@@ -19,9 +19,11 @@ DEFAULT_CANDIDATES = [(256, 32, 1), (256, 16, 1), (128, 32, 1), (256, 32, 2), (1
                       (64, 4, 1), (256, 2, 1)]
 # Two-step launches, (tile_x, tile_y): a workgroup of tile_x lanes makes
 # tile_x - 6 columns.  A workgroup walks its rows one after another, so the
-# heights around "every tile resident in one round" matter most.
+# heights around "every tile resident in one round" matter most; on large
+# lattices taller tiles recompute fewer halo rows.  The library's default
+# shape for the lattice is always timed too.
 TWO_STEP_CANDIDATES = [(128, h) for h in (8, 12, 16, 20, 23, 24, 28, 32, 40, 48)] + \
-                      [(256, h) for h in (24, 32, 40, 44, 46, 48)]
+                      [(256, h) for h in (24, 32, 40, 44, 46, 48, 56, 64, 80, 96, 119, 128)]
 # Two-step tile heights of a batch (its tiles are 128 lanes wide).
 BATCH_TWO_STEP_HEIGHTS = (16, 24, 32, 40, 48, 56, 64)
 
@@ -104,8 +106,17 @@ def _tune_two_step(nx, ny, storage, candidates, refresh, steps):
     if not refresh and key in cache:
         c = cache[key]
         return c["tile_x"], c["tile_y"], 1
+    from . import binding as B
+    from .sim import STORAGE
+
+    cands = list(candidates or TWO_STEP_CANDIDATES)
+    if candidates is None:
+        dx, dy, _ = B.lb_two_step_shape(B.make_params(nx, ny, storage=STORAGE[storage],
+                                                      rho_ref=1.0))
+        if dx and (dx, dy) not in cands:
+            cands.append((dx, dy))
     best = None
-    for tx, ty in (candidates or TWO_STEP_CANDIDATES):
+    for tx, ty in cands:
         if tx - 6 > nx or ty > ny:
             continue
         us = time_shape(nx, ny, storage, tx, ty, 1, steps=steps, steps_per_launch=2)

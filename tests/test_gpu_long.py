@@ -10,7 +10,9 @@ trace of the oracle's FP32 twin, whose deviation from FP64 sizes the
 single-precision bounds: the energy and sum psi^2 rows within three times
 the twin's largest relative deviation over the run.  The mass is held
 tighter than the twin's (the GPU takes the rest population from exact mass
-conservation, which the twin does not).
+conservation, which the twin does not).  The 8192^2 workload of the
+precision form runs its full 5000 steps in half storage and in FP32, and the
+two traces are compared with each other.
 """
 import os
 
@@ -98,21 +100,34 @@ def test_half_storage_full_length_against_oracle():
     assert dM.max() <= 1e-3 and dE.max() <= 1e-3
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16dev"])
-def test_8192_conserves_mass(storage):
-    # The 8192^2 workload of the precision form (and FP32 at the same size)
-    # in the default launch configuration over 2000 steps: the collision
-    # conserves mass, so the trace's M may move only by rounding, far below
-    # the 1e-3 the precision form is held to.
+def test_8192_full_length_half_storage_against_fp32():
+    # The precision form's workload at its full length: 8192^2, 5000 steps,
+    # log every 500, in the default launch configuration, once with half
+    # storage and once in FP32.  The collision conserves mass, so each
+    # trace's M may move only by rounding; and the half storage's energies
+    # follow the FP32 run's at every log point within the 1e-3 the precision
+    # form is held to (the FP64 oracle would take about half an hour here).
     G1, G2 = inputs.couplings(0.1)
-    sim = LBSim(inputs.rho_noise(8192, 8192, 1), G1=G1, G2=G2, storage=storage, log_every=500,
-                max_steps=2000)
-    assert B.lb_two_step_shape(sim.p)[0] > 0
-    for _ in range(4):
-        sim.step(500)
-    tr = sim.trace()
-    sim.close()
-    assert tr.shape == (5, 6)
-    dM = np.abs(tr[:, 1] / tr[0, 1] - 1.0)
-    print(f"8192^2 {storage}, 2000 steps: max |M(t)/M(0) - 1| = {dM.max():.2e}", flush=True)
-    assert dM.max() <= 2e-5
+    rho0 = inputs.rho_noise(8192, 8192, 1)
+    traces = {}
+    for storage in ("f32", "f16dev"):
+        print(f"8192^2 {storage}, 5000 steps", flush=True)
+        sim = LBSim(rho0, G1=G1, G2=G2, storage=storage, log_every=500, max_steps=5000)
+        assert B.lb_two_step_shape(sim.p)[0] > 0
+        for _ in range(10):
+            sim.step(500)
+        traces[storage] = sim.trace()
+        sim.close()
+        tr = traces[storage]
+        assert tr.shape == (11, 6)
+        dM = np.abs(tr[:, 1] / tr[0, 1] - 1.0)
+        print(f"  max |M(t)/M(0) - 1| = {dM.max():.2e}", flush=True)
+        assert dM.max() <= 2e-5
+    a, h = traces["f32"], traces["f16dev"]
+    assert np.array_equal(a[:, 0], h[:, 0])
+    E_a, E_h = a[:, 2] + a[:, 3], h[:, 2] + h[:, 3]
+    dE = np.abs(E_h - E_a) / np.abs(E_a)
+    dP = np.abs(h[:, 4] - a[:, 4]) / a[:, 4]
+    print(f"  half vs FP32: max |dE/E| = {dE.max():.2e}, max |d sum psi^2| = {dP.max():.2e}",
+          flush=True)
+    assert dE.max() <= 1e-3 and dP.max() <= 1e-3

@@ -163,13 +163,14 @@ def test_full_sweep_against_oracle():
         batch.close()
 
 
-@pytest.mark.parametrize("storage", ["f32", "f16dev"])
-def test_full_sweep_conserves_mass(storage):
-    """The 96-lattice sweep over 2000 steps in the default launch
-    configuration (plain steps two per launch): every lattice keeps its
-    mass up to rounding at every log point, |M(t)/M(0) - 1| <= 2e-5 in
-    FP32 and <= 1e-4 in half storage (its stochastically rounded rest
-    population moves the mass of a 128^2 lattice by a few 1e-5 in 2000
+@pytest.mark.parametrize("storage,steps", [("f32", 10000), ("f16dev", 2000)])
+def test_full_sweep_conserves_mass(storage, steps):
+    """The 96-lattice sweep in the default launch configuration (plain steps
+    two per launch), in FP32 over its full 10000 steps and in half storage
+    over 2000: every lattice keeps its mass up to rounding at every log
+    point, |M(t)/M(0) - 1| <= 2e-5 in FP32 and <= 1e-4 in half storage (its
+    stochastically rounded rest population moves the mass of a 128^2
+    lattice by a few 1e-5 in 2000 steps, growing as the square root of the
     steps; the precision form is held to 1e-3)."""
     spec = inputs.batched_lattices()
     lats = []
@@ -180,15 +181,16 @@ def test_full_sweep_conserves_mass(storage):
     stream = torch.cuda.Stream()
     with torch.cuda.stream(stream):
         batch = LBBatch(lats, storage=storage, tile_x=128, tile_rows=2, log_every=500,
-                        max_steps=2000)
+                        max_steps=steps)
         assert batch.two_step_shape()[0] == 128
-        batch.step(2000)
+        batch.step(steps)
         worst = 0.0
         for k in range(len(lats)):
             tr = batch[k].trace()
-            assert tr.shape == (5, 6)
+            assert tr.shape == (steps // 500 + 1, 6)
             dM = float(np.max(np.abs(tr[:, 1] / tr[0, 1] - 1.0)))
             worst = max(worst, dM)
             assert dM <= (2e-5 if storage == "f32" else 1e-4), (k, spec[k], dM)
-        print(f"96-lattice sweep {storage}, 2000 steps: max |M(t)/M(0) - 1| = {worst:.2e}", flush=True)
+        print(f"96-lattice sweep {storage}, {steps} steps: max |M(t)/M(0) - 1| = {worst:.2e}",
+              flush=True)
         batch.close()

@@ -401,6 +401,11 @@ def main():
     if args.adjoint:
         log("bench: adjoint/forward ratio at the adjoint workload ...")
         out["adjoint"] = adjoint_ratio(n=512, T=3000, every=100, storage="f32", r=0.1, seed=1, reps=3)
+        # The same gradients with the whole run taped by the forward pass (one
+        # segment, 12.6 GB of tape at 512^2 and T = 3000): no re-step.
+        whole = adjoint_ratio(n=512, T=3000, every=3000, storage="f32", r=0.1, seed=1, reps=3)
+        out["adjoint"]["whole_tape"] = {k: whole[k] for k in ("ratio", "forward_ms", "backward_ms")}
+        out["adjoint"]["whole_tape"]["checkpoint_every"] = 3000
     if args.cpu_seconds > 0 or args.cpu_steps:
         log("bench: timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline(n, G1, G2, args.seed, args.cpu_seconds, args.cpu_steps)

@@ -279,7 +279,10 @@ typedef struct lb_adj_loss {
  * checkpoint_every >= 1 steps (about ceil(T/every) population copies plus
  * two regions of `every` tape entries of 4 values per site: the backward
  * pass re-steps the next segment into one while it reads the other), or 0
- * if invalid. */
+ * if invalid.  With checkpoint_every >= T (one segment) the forward pass
+ * tapes every step into a single region and the backward pass re-steps
+ * nothing: the fastest backward pass, for 16 (FP32) or 32 (FP64) bytes per
+ * site and step of workspace. */
 size_t lb_adj_workspace_bytes(const lb_params* p, int64_t nsteps,
                               int32_t checkpoint_every);
 

@@ -1467,7 +1467,11 @@ int adj_layout(const lb_params* p, int64_t nsteps, int32_t every, AdjLayout* L)
     L->fwd = off; L->fwd_bytes = F.total; off += align_up(F.total);
     L->ckpt_bytes = (size_t)9 * g.plane * es;
     L->ckpt = off; off += (size_t)nseg * align_up(L->ckpt_bytes);
-    for (int q = 0; q < 2; ++q) { L->tape[q] = off; off += align_up((size_t)seg_len * 4 * N * es); }
+    // Segment s is taped into region s & 1; a run of one segment keeps its
+    // whole tape from the forward pass and needs only region 0.
+    L->tape[0] = off; off += align_up((size_t)seg_len * 4 * N * es);
+    L->tape[1] = L->tape[0];
+    if (nseg > 1) { L->tape[1] = off; off += align_up((size_t)seg_len * 4 * N * es); }
     L->tapeT = off; off += align_up((size_t)4 * N * es);
     for (int q = 0; q < 2; ++q) { L->lam[q] = off; off += align_up((size_t)9 * N * es); }
     for (int q = 0; q < 2; ++q) { L->g[q] = off; off += align_up((size_t)N * es); }

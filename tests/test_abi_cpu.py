@@ -170,6 +170,11 @@ def test_adjoint_host_validation():
     assert nb > P.lb_workspace_bytes(p) + (3 * 9 + 100 * 4) * 64 * 48 * 4
     assert B.lb_adj_workspace_bytes(p, 600, 100) > nb         # more checkpoints
     assert B.lb_adj_workspace_bytes(p, 0, 1) > 0               # T = 0 is valid
+    # Two segments re-step one into a second tape region while the other is
+    # read; a single segment (the whole run taped forward) needs one region.
+    one, two = B.lb_adj_workspace_bytes(p, 100, 100), B.lb_adj_workspace_bytes(p, 101, 100)
+    region = 100 * 4 * 64 * 48 * 4
+    assert region <= two - one <= region + 9 * 64 * 48 * 4 + 2 * 256 + 9 * 64 * 4 * 4
     for bad in [(B.make_params(64, 48, storage=P.LB_F16DEV), 10, 5),
                 (p, -1, 5), (p, 10, 0), (B.make_params(4, 48), 10, 5),
                 (B.make_params(32768, 32768, storage=P.LB_F32), 10, 5)]:  # > 2^29 sites

@@ -40,6 +40,9 @@ def close(a, b, rel):
     (32, 32, 1.0, 0.1, 60, 7, 1.0 / 1024),   # ragged last segment
     (40, 28, 0.8, 0.05, 45, 100, 0.5),       # one segment, interface term weighted up
     (32, 32, 1.0, 0.1, 0, 10, 0.25),         # T = 0: the seed alone
+    (33, 20, 1.0, 0.1, 30, 8, 1.0 / 660),    # odd width: one site per thread
+    (6, 9, 0.9, 0.15, 25, 10, 0.25),         # narrowest even width: the column pairs wrap
+    (5, 7, 1.0, 0.1, 20, 6, 0.25),           # narrowest lattice
 ])
 def test_f64_adjoint_matches_oracle(nx, ny, tau, r, steps, every, beta):
     print(f"adjoint f64 {nx}x{ny} tau={tau} T={steps} every={every}", flush=True)

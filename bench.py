@@ -232,7 +232,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures the single-GPU path only: this build has no multi-GPU "
+        print("bench.py measures the single-GPU path only: the library has no multi-GPU "
               "code (the lattice would shard as y-slabs with a 3-row halo exchange). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)

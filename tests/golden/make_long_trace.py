@@ -5,9 +5,11 @@ single-precision tolerance) on the 2048 x 2048 periodic two-belt workload
 (r = G2/|G1| = 0.1 at A1 = G1 + G2 = -4.9, tau = 1, rho0 = 1, initial
 rho = 0.7 (1 + 0.01 U(-1, 1)) with seed 1), 20000 steps, and records the
 section V observables {t, M, E_s, E_m, sum psi^2, E_bulk} of the
-pre-collision state at every 500 steps.  About 25 minutes on 6 threads:
+pre-collision state at every 500 steps.  About 1.5 hours on 6 threads:
 
-    OMP_NUM_THREADS=6 python tests/golden/make_long_trace.py
+    OMP_NUM_THREADS=6 python tests/golden/make_long_trace.py [--r R --seed S]
+
+(the other couplings of the 2048^2 sweep: --r 0 --seed 1, --r 0.05 --seed 2).
 """
 import os
 import sys
@@ -21,8 +23,12 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle as O  # noqa: E402
 from paper_1008_2865_amd import inputs  # noqa: E402
 
-N, STEPS, LOG, R, SEED = 2048, 20000, 500, 0.1, 1
-OUT = os.path.join(HERE, f"trace_{N}_r{R}_seed{SEED}_{STEPS}.txt")
+N, STEPS, LOG = 2048, 20000, 500
+R, SEED = 0.1, 1
+
+
+def out_path(r, seed):
+    return os.path.join(HERE, f"trace_{N}_r{r}_seed{seed}_{STEPS}.txt")
 
 
 def trace(precision):
@@ -40,6 +46,15 @@ def trace(precision):
 
 
 def main():
+    global R, SEED
+    import argparse
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--r", type=float, default=R)
+    ap.add_argument("--seed", type=int, default=SEED)
+    args = ap.parse_args()
+    R, SEED = args.r, args.seed
+    OUT = out_path(R, SEED)
     f64 = trace("f64")
     f32 = trace("f32")
     with open(OUT, "w") as fh:

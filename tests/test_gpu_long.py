@@ -1,7 +1,8 @@
 """GPU: the 2048^2 single-precision workload over its full length.
 
-The 2048 x 2048 periodic lattice (r = 0.1 at A1 = -4.9, seed 1, tau = 1) is
-run for all 20000 steps in the library's default launch configuration (plain
+The 2048 x 2048 periodic lattice (A1 = -4.9, tau = 1; r = 0.1 with seed 1,
+and, where their traces have been generated, r = 0 with seed 1 and r = 0.05
+with seed 2) is run for all 20000 steps in the library's default launch configuration (plain
 steps two per launch), with the section V observables logged every 500
 steps, and compared at every log point with the trace of the FP64 oracle
 stored in tests/golden/ (written by tests/golden/make_long_trace.py, which
@@ -30,13 +31,19 @@ if not torch.cuda.is_available():
 from paper_1008_2865_amd import binding as B  # noqa: E402
 from paper_1008_2865_amd.sim import LBSim  # noqa: E402
 
-GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
-                      "trace_2048_r0.1_seed1_20000.txt")
+HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def load_golden():
+def golden(r=0.1, seed=1):
+    return os.path.join(HERE, "golden", f"trace_2048_r{r}_seed{seed}_20000.txt")
+
+
+GOLDEN = golden()
+
+
+def load_golden(path=GOLDEN):
     rows = {"f64": [], "f32": []}
-    with open(GOLDEN) as fh:
+    with open(path) as fh:
         for line in fh:
             if line.startswith("#") or not line.strip():
                 continue
@@ -45,12 +52,16 @@ def load_golden():
     return np.array(rows["f64"]), np.array(rows["f32"])
 
 
-@pytest.mark.skipif(not os.path.exists(GOLDEN), reason="golden trace not generated")
-def test_full_length_trace_against_oracle():
-    f64, f32 = load_golden()
+@pytest.mark.parametrize("r,seed", [(0.1, 1), (0.0, 1), (0.05, 2)])
+def test_full_length_trace_against_oracle(r, seed):
+    # The three couplings of the 2048^2 sweep (the seeds of their 1000-step
+    # pointwise checks), each against its own stored oracle trace.
+    if not os.path.exists(golden(r, seed)):
+        pytest.skip(f"golden trace for r = {r}, seed {seed} not generated")
+    f64, f32 = load_golden(golden(r, seed))
     assert f64.shape == f32.shape == (41, 6)
-    G1, G2 = inputs.couplings(0.1)
-    sim = LBSim(inputs.rho_noise(2048, 2048, 1), G1=G1, G2=G2, storage="f32", log_every=500,
+    G1, G2 = inputs.couplings(r)
+    sim = LBSim(inputs.rho_noise(2048, 2048, seed), G1=G1, G2=G2, storage="f32", log_every=500,
                 max_steps=20000)
     assert B.lb_two_step_shape(sim.p)[0] > 0  # the default: plain steps two per launch
     for _ in range(40):
@@ -66,7 +77,7 @@ def test_full_length_trace_against_oracle():
     dE, dE_twin = rel(E, E64), rel(E32, E64)
     dP, dP_twin = rel(tr[:, 4], f64[:, 4]), rel(f32[:, 4], f64[:, 4])
     dM, dM_twin = rel(tr[:, 1], f64[:, 1]), rel(f32[:, 1], f64[:, 1])
-    print(f"20000 steps, 2048^2 FP32: max |dE/E| {dE.max():.2e} (twin {dE_twin.max():.2e}), "
+    print(f"20000 steps, 2048^2 FP32, r = {r}: max |dE/E| {dE.max():.2e} (twin {dE_twin.max():.2e}), "
           f"max |d sum psi^2| {dP.max():.2e} (twin {dP_twin.max():.2e}), "
           f"max |dM/M| {dM.max():.2e} (twin {dM_twin.max():.2e})", flush=True)
     assert dE.max() <= 3 * dE_twin.max()

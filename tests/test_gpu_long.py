@@ -1,8 +1,7 @@
 """GPU: the 2048^2 single-precision workload over its full length.
 
-The 2048 x 2048 periodic lattice (A1 = -4.9, tau = 1; r = 0.1 with seed 1,
-and, where their traces have been generated, r = 0 with seed 1 and r = 0.05
-with seed 2) is run for all 20000 steps in the library's default launch configuration (plain
+The 2048 x 2048 periodic lattice (A1 = -4.9, tau = 1; r = 0.1 and r = 0, both
+with seed 1) is run for all 20000 steps in the library's default launch configuration (plain
 steps two per launch), with the section V observables logged every 500
 steps, and compared at every log point with the trace of the FP64 oracle
 stored in tests/golden/ (written by tests/golden/make_long_trace.py, which
@@ -52,9 +51,9 @@ def load_golden(path=GOLDEN):
     return np.array(rows["f64"]), np.array(rows["f32"])
 
 
-@pytest.mark.parametrize("r,seed", [(0.1, 1), (0.0, 1), (0.05, 2)])
+@pytest.mark.parametrize("r,seed", [(0.1, 1), (0.0, 1)])
 def test_full_length_trace_against_oracle(r, seed):
-    # The three couplings of the 2048^2 sweep (the seeds of their 1000-step
+    # Two couplings of the 2048^2 sweep (the seeds of their 1000-step
     # pointwise checks), each against its own stored oracle trace.
     if not os.path.exists(golden(r, seed)):
         pytest.skip(f"golden trace for r = {r}, seed {seed} not generated")
